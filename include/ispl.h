@@ -1,0 +1,149 @@
+/*
+ * ispl.h - C ABI of the incoherent-scatter plasma-line spectrum library
+ * (MI355X / gfx950).
+ *
+ * The library computes, for a batch of transmitted pulses and a set of radar
+ * range gates, the incoherently integrated power spectrum
+ *
+ *   S[g][k] = sum_{p < P} | sum_{n < L} conj(c_p[n]) * x_p[g0 + g*s + n]
+ *                                      * exp(-2 pi i k n / N) |^2
+ *
+ * i.e. the conjugated transmit code is multiplied into one range gate of the
+ * echo, the product is Fourier transformed, squared in modulus and added over
+ * pulses (Hilliard, Vierinen & Erickson, "GPGPU Acceleration of Incoherent
+ * Scatter Radar Plasma Line Analysis", Section 2.2, Eqs. 7-8 and the
+ * processing recipe after them; Section 3.2 for the decode, transform and
+ * accumulate steps).  It then finds the plasma line of every gate as the peak
+ * of S over a frequency band.
+ *
+ * Conventions for every call:
+ *   - All array pointers are DEVICE pointers (hipMalloc or torch tensors) and
+ *     stay owned by the caller; they must stay valid until the work queued on
+ *     `stream` has completed.  Pointers must be aligned to their element size
+ *     (4 bytes for ci16 samples and float/int32 outputs, 8 bytes for complex64).
+ *   - Work is queued asynchronously on `stream` (a hipStream_t; NULL = the
+ *     null stream).  The caller synchronises.
+ *   - Every argument is validated before anything is queued.  On any error
+ *     nothing is launched and no output is written; the call returns a
+ *     non-zero ispl_status and ispl_last_error() describes the problem.
+ *   - Nothing throws or aborts across this ABI.
+ *   - A context is not thread-safe: one thread at a time per context.
+ *   - Results are bit-identical from run to run for the same context,
+ *     arguments and device (no atomics, fixed reduction order).
+ */
+#ifndef ISPL_H
+#define ISPL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ISPL_ABI_VERSION 1
+
+typedef struct ispl_ctx ispl_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  ISPL_OK = 0,
+  ISPL_ERR_INVALID_ARG = 1,  /* bad pointer, size or layout */
+  ISPL_ERR_UNSUPPORTED = 2,  /* valid, but outside what this build implements */
+  ISPL_ERR_OUT_OF_MEMORY = 3,
+  ISPL_ERR_DEVICE = 4        /* no usable gfx950 device, or a HIP runtime error */
+} ispl_status;
+
+typedef enum {
+  ISPL_SAMPLES_C64 = 0,  /* complex64: float re, float im per sample */
+  ISPL_SAMPLES_CI16 = 1  /* complex int16: int16 re, int16 im per sample (raw ADC) */
+} ispl_sample_type;
+
+/*
+ * Fixed geometry of one experiment (Section 4 describes the paper's: 16384-
+ * sample codes, 250,000-sample echo rows, 4096 gates with a step of 25 starting
+ * at the first sample, FFT length 16384).
+ */
+typedef struct {
+  int32_t abi_version;  /* must be ISPL_ABI_VERSION */
+  int32_t code_len;     /* L >= 1: transmit code length in samples */
+  int32_t fft_len;      /* N: power of two, L <= N.  This build: 1024 <= N <= 65536
+                           and L <= 1024 (other valid shapes: ISPL_ERR_UNSUPPORTED) */
+  int32_t n_gates;      /* G >= 1 range gates */
+  int32_t gate_step;    /* s >= 1 samples between consecutive gate starts */
+  int32_t first_gate;   /* g0 >= 0: echo sample where gate 0 starts */
+  int64_t pulse_stride; /* samples from one echo row to the next;
+                           must be >= g0 + (G - 1) * s + L */
+  int32_t sample_type;  /* ispl_sample_type */
+  int32_t max_pulses;   /* >= 1: largest n_pulses a call may pass (sizes scratch) */
+  int32_t device;       /* HIP device ordinal */
+} ispl_config;
+
+/* Validates `cfg`, selects `cfg->device`, builds the twiddle table and the
+ * scratch buffers the plan needs, and returns a new context in *out.
+ * Config errors are reported before the device is touched.  Returns
+ * ISPL_ERR_DEVICE when the device is missing or is not gfx950. */
+ispl_status ispl_create(const ispl_config* cfg, ispl_ctx** out);
+
+/*
+ * Integrated spectra of n_pulses pulses (Eqs. 7-8; Section 3.2):
+ *   samples   device [n_pulses][pulse_stride] samples of `sample_type`,
+ *             interleaved (re, im).  Gate g of pulse p reads samples
+ *             p*pulse_stride + g0 + g*s + n, n < L.
+ *   tx_code   device complex64 (re, im float pairs): [n_pulses][L] when
+ *             tx_per_pulse != 0 (one code per pulse), else [L] shared by all.
+ *   spectra   device float [n_gates][fft_len], natural FFT order (bin k is
+ *             frequency k*fs/N for k < N/2, (k-N)*fs/N above), unnormalised
+ *             forward transform exp(-2 pi i k n / N), |X|^2 summed (not
+ *             averaged) over the pulses.
+ *   accumulate  0: spectra = sum;  1: spectra += sum (resumable integration).
+ *   n_pulses  0 <= n_pulses <= max_pulses.  With 0 pulses the sum is empty:
+ *             spectra is zeroed (accumulate = 0) or left as is (accumulate = 1).
+ * Arithmetic: decode, transform, power and accumulation in FP32.
+ */
+ispl_status ispl_integrate_spectra(ispl_ctx* ctx, const void* samples,
+                                   const float* tx_code, int32_t tx_per_pulse,
+                                   int32_t n_pulses, float* spectra,
+                                   int32_t accumulate, void* stream);
+
+/*
+ * Plasma-line pick per gate (the line frequency is the quantity the spectra
+ * are computed for, Section 2.1): peak_bin[g] = the lowest bin k in the band
+ * attaining max_k spectra[g][k]; peak_power[g] = that maximum.
+ *   spectra   device float [n_gates][fft_len] (e.g. from ispl_integrate_spectra)
+ *   band      bins [bin_lo, bin_hi) in natural order, 0 <= bin_lo < N,
+ *             0 < bin_hi <= N, bin_lo != bin_hi; bin_lo > bin_hi wraps through
+ *             N, i.e. [bin_lo, N) then [0, bin_hi).  The full band is
+ *             bin_lo = 0, bin_hi = N.
+ *   peak_bin  device int32 [n_gates]
+ *   peak_power device float [n_gates], or NULL when not wanted.
+ * Values are compared as FP32; spectra holding NaN give an unspecified bin.
+ */
+ispl_status ispl_find_plasma_line(ispl_ctx* ctx, const float* spectra,
+                                  int32_t bin_lo, int32_t bin_hi,
+                                  int32_t* peak_bin, float* peak_power,
+                                  void* stream);
+
+/* Frees the context and its device memory (synchronises its device first).
+ * NULL is a no-op. */
+void ispl_destroy(ispl_ctx* ctx);
+
+/* Launch plan the library would use for n_pulses pulses with this config;
+ * host-only (no device call), for tests and tooling.  Fills, when non-NULL:
+ * chunks = number of pulse chunks integrated side by side (1 = no partial
+ * buffers), waves_per_block, blocks = workgroups of the fused launch. */
+ispl_status ispl_plan(const ispl_config* cfg, int32_t n_pulses, int32_t* chunks,
+                      int32_t* waves_per_block, int32_t* blocks);
+
+/* Static string for a status code. */
+const char* ispl_status_string(ispl_status s);
+
+/* Detail of the last error on the calling thread ("" if none). */
+const char* ispl_last_error(void);
+
+/* ABI version the library was built with (ISPL_ABI_VERSION). */
+int32_t ispl_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ISPL_H */

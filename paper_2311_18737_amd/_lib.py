@@ -1,0 +1,102 @@
+"""ctypes declarations of the C ABI in include/ispl.h (argument marshalling only)."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG_DIR, "lib", "libispl.so")
+
+ISPL_ABI_VERSION = 1
+
+ISPL_OK = 0
+ISPL_ERR_INVALID_ARG = 1
+ISPL_ERR_UNSUPPORTED = 2
+ISPL_ERR_OUT_OF_MEMORY = 3
+ISPL_ERR_DEVICE = 4
+
+ISPL_SAMPLES_C64 = 0
+ISPL_SAMPLES_CI16 = 1
+
+EXPORTED = (
+    "ispl_create",
+    "ispl_integrate_spectra",
+    "ispl_find_plasma_line",
+    "ispl_destroy",
+    "ispl_plan",
+    "ispl_status_string",
+    "ispl_last_error",
+    "ispl_abi_version",
+)
+
+
+class IsplConfig(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_int32),
+        ("code_len", ctypes.c_int32),
+        ("fft_len", ctypes.c_int32),
+        ("n_gates", ctypes.c_int32),
+        ("gate_step", ctypes.c_int32),
+        ("first_gate", ctypes.c_int32),
+        ("pulse_stride", ctypes.c_int64),
+        ("sample_type", ctypes.c_int32),
+        ("max_pulses", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+    ]
+
+
+class IsplError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {detail}")
+
+
+STATUS_NAMES = {
+    ISPL_OK: "ISPL_OK",
+    ISPL_ERR_INVALID_ARG: "ISPL_ERR_INVALID_ARG",
+    ISPL_ERR_UNSUPPORTED: "ISPL_ERR_UNSUPPORTED",
+    ISPL_ERR_OUT_OF_MEMORY: "ISPL_ERR_OUT_OF_MEMORY",
+    ISPL_ERR_DEVICE: "ISPL_ERR_DEVICE",
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Loads the built HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"HIP library {path} is missing: build it with "
+            "`python -m paper_2311_18737_amd.build` (there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.ispl_create.argtypes = [ctypes.POINTER(IsplConfig), ctypes.POINTER(vp)]
+    lib.ispl_create.restype = i32
+    lib.ispl_integrate_spectra.argtypes = [vp, vp, vp, i32, i32, vp, i32, vp]
+    lib.ispl_integrate_spectra.restype = i32
+    lib.ispl_find_plasma_line.argtypes = [vp, vp, i32, i32, vp, vp, vp]
+    lib.ispl_find_plasma_line.restype = i32
+    lib.ispl_destroy.argtypes = [vp]
+    lib.ispl_destroy.restype = None
+    lib.ispl_plan.argtypes = [ctypes.POINTER(IsplConfig), i32, ctypes.POINTER(i32),
+                              ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.ispl_plan.restype = i32
+    lib.ispl_status_string.argtypes = [i32]
+    lib.ispl_status_string.restype = ctypes.c_char_p
+    lib.ispl_last_error.argtypes = []
+    lib.ispl_last_error.restype = ctypes.c_char_p
+    lib.ispl_abi_version.argtypes = []
+    lib.ispl_abi_version.restype = i32
+    del i64
+    _lib = lib
+    return lib
+
+
+def check(status: int, where: str) -> None:
+    if status != ISPL_OK:
+        detail = load_library().ispl_last_error().decode(errors="replace")
+        raise IsplError(status, where, detail)

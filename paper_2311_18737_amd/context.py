@@ -1,0 +1,169 @@
+"""Python binding of the plasma-line spectrum library.
+
+Argument marshalling only: tensors are checked and their device pointers and
+the stream handle are handed to the C ABI (include/ispl.h); every arithmetic
+step runs in the HIP kernels.  torch supplies device memory and streams.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import IsplConfig, check, load_library
+
+_SAMPLE_TYPES = {"c64": _lib.ISPL_SAMPLES_C64, "ci16": _lib.ISPL_SAMPLES_CI16}
+
+
+def make_config(*, code_len: int, fft_len: int, n_gates: int, gate_step: int = 25,
+                first_gate: int = 0, pulse_stride: Optional[int] = None,
+                sample_type: str = "c64", max_pulses: int = 1, device: int = 0) -> IsplConfig:
+    if sample_type not in _SAMPLE_TYPES:
+        raise ValueError(f"sample_type must be one of {sorted(_SAMPLE_TYPES)}")
+    if pulse_stride is None:
+        pulse_stride = first_gate + (n_gates - 1) * gate_step + code_len
+    return IsplConfig(abi_version=_lib.ISPL_ABI_VERSION, code_len=code_len, fft_len=fft_len,
+                      n_gates=n_gates, gate_step=gate_step, first_gate=first_gate,
+                      pulse_stride=pulse_stride, sample_type=_SAMPLE_TYPES[sample_type],
+                      max_pulses=max_pulses, device=device)
+
+
+def plan(n_pulses: int, **cfg) -> dict:
+    """Launch plan for n_pulses (host-only): chunks, waves per block, blocks."""
+    lib = load_library()
+    c = make_config(**cfg)
+    chunks, wpb, blocks = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib.ispl_plan(ctypes.byref(c), n_pulses, ctypes.byref(chunks), ctypes.byref(wpb),
+                        ctypes.byref(blocks)), "ispl_plan")
+    return {"chunks": chunks.value, "waves_per_block": wpb.value, "blocks": blocks.value}
+
+
+def _stream_handle(stream, device) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return int(stream.cuda_stream)
+
+
+def _require(cond: bool, msg: str) -> None:
+    if not cond:
+        raise ValueError(msg)
+
+
+class Context:
+    """One experiment geometry on one GPU (ispl_create / ispl_destroy)."""
+
+    def __init__(self, *, code_len: int, fft_len: int, n_gates: int, gate_step: int = 25,
+                 first_gate: int = 0, pulse_stride: Optional[int] = None,
+                 sample_type: str = "c64", max_pulses: int, device: int = 0):
+        self._lib = load_library()
+        self.cfg = make_config(code_len=code_len, fft_len=fft_len, n_gates=n_gates,
+                               gate_step=gate_step, first_gate=first_gate,
+                               pulse_stride=pulse_stride, sample_type=sample_type,
+                               max_pulses=max_pulses, device=device)
+        self.sample_type = sample_type
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        check(self._lib.ispl_create(ctypes.byref(self.cfg), ctypes.byref(h)), "ispl_create")
+        self._h = h
+
+    # geometry
+    code_len = property(lambda self: self.cfg.code_len)
+    fft_len = property(lambda self: self.cfg.fft_len)
+    n_gates = property(lambda self: self.cfg.n_gates)
+    pulse_stride = property(lambda self: self.cfg.pulse_stride)
+    max_pulses = property(lambda self: self.cfg.max_pulses)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ispl_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _handle(self):
+        if self._h is None:
+            raise RuntimeError("context is closed")
+        return self._h
+
+    def _check_samples(self, samples: torch.Tensor) -> int:
+        _require(samples.device == self.device, f"samples must be on {self.device}")
+        _require(samples.is_contiguous(), "samples must be contiguous")
+        if self.sample_type == "c64":
+            _require(samples.dtype == torch.complex64 and samples.dim() == 2,
+                     "c64 samples must be complex64 [n_pulses][pulse_stride]")
+        else:
+            _require(samples.dtype == torch.int16 and samples.dim() == 3 and samples.shape[2] == 2,
+                     "ci16 samples must be int16 [n_pulses][pulse_stride][2]")
+        _require(samples.shape[1] == self.pulse_stride,
+                 f"samples rows must hold pulse_stride={self.pulse_stride} samples")
+        return samples.shape[0]
+
+    def integrate_spectra(self, samples: torch.Tensor, tx: torch.Tensor, *,
+                          out: Optional[torch.Tensor] = None, accumulate: bool = False,
+                          stream=None) -> torch.Tensor:
+        """S[g][k] = sum_p |FFT_N(conj(c_p) * gate window)|^2 (ispl_integrate_spectra).
+
+        samples: [P][pulse_stride] complex64, or int16 [P][pulse_stride][2].
+        tx: complex64 [P][L] (one code per pulse) or [L] / [1][L] (shared).
+        out: float32 [G][N]; allocated when None (accumulate needs it given).
+        """
+        h = self._handle()
+        n_pulses = self._check_samples(samples)
+        _require(tx.device == self.device and tx.is_contiguous(), "tx must be contiguous on device")
+        _require(tx.dtype == torch.complex64, "tx must be complex64")
+        if tx.dim() == 1:
+            tx = tx.unsqueeze(0)
+        _require(tx.dim() == 2 and tx.shape[1] == self.code_len, "tx must be [P or 1][code_len]")
+        per_pulse = tx.shape[0] != 1
+        _require(not per_pulse or tx.shape[0] == n_pulses, "tx rows must be 1 or n_pulses")
+        if out is None:
+            _require(not accumulate, "accumulate=True needs `out`")
+            out = torch.empty((self.n_gates, self.fft_len), dtype=torch.float32,
+                              device=self.device)
+        _require(out.device == self.device and out.dtype == torch.float32 and out.is_contiguous()
+                 and tuple(out.shape) == (self.n_gates, self.fft_len),
+                 "out must be contiguous float32 [n_gates][fft_len] on the device")
+        st = self._lib.ispl_integrate_spectra(
+            h, ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(tx.data_ptr()),
+            int(per_pulse), n_pulses, ctypes.c_void_p(out.data_ptr()), int(bool(accumulate)),
+            ctypes.c_void_p(_stream_handle(stream, self.device)))
+        check(st, "ispl_integrate_spectra")
+        return out
+
+    def find_plasma_line(self, spectra: torch.Tensor, bin_lo: int = 0,
+                         bin_hi: Optional[int] = None, *, want_power: bool = True,
+                         out_bins: Optional[torch.Tensor] = None,
+                         out_power: Optional[torch.Tensor] = None, stream=None):
+        """Per-gate peak bin (lowest bin among equal maxima) over [bin_lo, bin_hi),
+        wrapping through N when bin_lo > bin_hi (ispl_find_plasma_line)."""
+        h = self._handle()
+        if bin_hi is None:
+            bin_hi = self.fft_len
+        _require(spectra.device == self.device and spectra.dtype == torch.float32
+                 and spectra.is_contiguous()
+                 and tuple(spectra.shape) == (self.n_gates, self.fft_len),
+                 "spectra must be contiguous float32 [n_gates][fft_len] on the device")
+        if out_bins is None:
+            out_bins = torch.empty(self.n_gates, dtype=torch.int32, device=self.device)
+        if want_power and out_power is None:
+            out_power = torch.empty(self.n_gates, dtype=torch.float32, device=self.device)
+        pp = ctypes.c_void_p(out_power.data_ptr()) if want_power else ctypes.c_void_p(0)
+        st = self._lib.ispl_find_plasma_line(
+            h, ctypes.c_void_p(spectra.data_ptr()), int(bin_lo), int(bin_hi),
+            ctypes.c_void_p(out_bins.data_ptr()), pp,
+            ctypes.c_void_p(_stream_handle(stream, self.device)))
+        check(st, "ispl_find_plasma_line")
+        return out_bins, (out_power if want_power else None)

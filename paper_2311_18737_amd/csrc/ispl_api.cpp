@@ -1,0 +1,359 @@
+// C ABI of the plasma-line spectrum library: argument validation, launch
+// planning, context-owned device state (twiddle table, chunk partials).
+// Declared in include/ispl.h.
+
+#include "ispl.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ispl_internal.h"
+
+struct ispl_ctx {
+  ispl_config cfg;
+  int32_t chunks_max;   // largest chunk count any call may plan
+  float* twiddle;       // complex64 pairs, N entries
+  float* partial;       // chunks_max * G * N floats (nullptr when chunks_max == 1)
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ispl_status fail(ispl_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
+ispl_status fail(ispl_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+ispl_status ok() {
+  g_last_error.clear();
+  return ISPL_OK;
+}
+
+ispl_status hip_fail(hipError_t e, const char* what) {
+  return fail(ISPL_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int64_t v) {
+  int r = 0;
+  while ((int64_t{1} << r) < v) ++r;
+  return r;
+}
+
+// Planning constants of the target: MI355X has 256 compute units with 160 KiB
+// of LDS each; a wave of the fused kernel may use up to 128 VGPRs, so at most
+// 16 of its waves fit on one compute unit.
+constexpr int kComputeUnits = 256;
+constexpr int kLdsPerCu = 160 * 1024;
+constexpr int kMaxWavesPerCu = 16;
+constexpr int kMaxChunks = 256;
+constexpr int64_t kMaxPartialBytes = int64_t{1} << 30;
+
+struct Plan {
+  int rw;         // waves per workgroup
+  int zgroups;    // workgroups per gate and chunk (R / rw)
+  int chunks;     // pulse chunks
+  int64_t blocks; // workgroups of the fused launch
+};
+
+Plan make_plan(const ispl_config& c, int32_t n_pulses) {
+  Plan pl{};
+  const int r = c.fft_len / ispl::SUB;
+  pl.rw = r < ispl::MAX_WAVES_PER_BLOCK ? r : ispl::MAX_WAVES_PER_BLOCK;
+  pl.zgroups = r / pl.rw;
+  int per_cu = kLdsPerCu / ispl::fused_lds_bytes(pl.rw);
+  if (per_cu * pl.rw > kMaxWavesPerCu) per_cu = kMaxWavesPerCu / pl.rw;
+  if (per_cu < 1) per_cu = 1;
+  const int64_t slots = int64_t{kComputeUnits} * per_cu;
+  const int64_t base = static_cast<int64_t>(c.n_gates) * pl.zgroups;
+  // enough workgroups for two rounds over the chip, but never empty chunks
+  int64_t chunks = 1;
+  if (base < 2 * slots) chunks = (2 * slots + base - 1) / base;
+  if (chunks > n_pulses) chunks = n_pulses;
+  if (chunks > kMaxChunks) chunks = kMaxChunks;
+  const int64_t gn_bytes = static_cast<int64_t>(c.n_gates) * c.fft_len * 4;
+  if (chunks > 1 && chunks * gn_bytes > kMaxPartialBytes) chunks = kMaxPartialBytes / gn_bytes;
+  if (chunks < 1) chunks = 1;
+  pl.chunks = static_cast<int>(chunks);
+  pl.blocks = base * pl.chunks;
+  return pl;
+}
+
+ispl_status validate_config(const ispl_config* c) {
+  if (!c) return fail(ISPL_ERR_INVALID_ARG, "config is NULL");
+  if (c->abi_version != ISPL_ABI_VERSION)
+    return fail(ISPL_ERR_INVALID_ARG, "abi_version %d, library is %d", c->abi_version,
+                ISPL_ABI_VERSION);
+  if (c->code_len < 1) return fail(ISPL_ERR_INVALID_ARG, "code_len %d < 1", c->code_len);
+  if (!is_pow2(c->fft_len))
+    return fail(ISPL_ERR_INVALID_ARG, "fft_len %d is not a power of two", c->fft_len);
+  if (c->code_len > c->fft_len)
+    return fail(ISPL_ERR_INVALID_ARG, "code_len %d > fft_len %d", c->code_len, c->fft_len);
+  if (c->n_gates < 1) return fail(ISPL_ERR_INVALID_ARG, "n_gates %d < 1", c->n_gates);
+  if (c->gate_step < 1) return fail(ISPL_ERR_INVALID_ARG, "gate_step %d < 1", c->gate_step);
+  if (c->first_gate < 0) return fail(ISPL_ERR_INVALID_ARG, "first_gate %d < 0", c->first_gate);
+  if (c->sample_type != ISPL_SAMPLES_C64 && c->sample_type != ISPL_SAMPLES_CI16)
+    return fail(ISPL_ERR_INVALID_ARG, "unknown sample_type %d", c->sample_type);
+  if (c->max_pulses < 1) return fail(ISPL_ERR_INVALID_ARG, "max_pulses %d < 1", c->max_pulses);
+  if (c->device < 0) return fail(ISPL_ERR_INVALID_ARG, "device %d < 0", c->device);
+  const int64_t need = static_cast<int64_t>(c->first_gate) +
+                       static_cast<int64_t>(c->n_gates - 1) * c->gate_step + c->code_len;
+  if (c->pulse_stride < need)
+    return fail(ISPL_ERR_INVALID_ARG,
+                "pulse_stride %lld < first_gate + (n_gates-1)*gate_step + code_len = %lld",
+                static_cast<long long>(c->pulse_stride), static_cast<long long>(need));
+  // what this build implements
+  if (c->fft_len < ispl::SUB || c->fft_len > 65536)
+    return fail(ISPL_ERR_UNSUPPORTED, "fft_len %d outside [1024, 65536]", c->fft_len);
+  if (c->code_len > ispl::SUB)
+    return fail(ISPL_ERR_UNSUPPORTED, "code_len %d > 1024", c->code_len);
+  // one 64-lane wave per (gate, bin class); keep the launch under 2^31 threads
+  if (static_cast<int64_t>(c->n_gates) * (c->fft_len / ispl::SUB) * 64 >= (int64_t{1} << 31))
+    return fail(ISPL_ERR_UNSUPPORTED, "n_gates %d too large for one launch", c->n_gates);
+  return ISPL_OK;
+}
+
+struct DeviceGuard {  // restores the caller's current device
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+// W_N^i = exp(-2 pi i / N)^i for i < N, from double-precision cos/sin of the
+// first octant and exact symmetries (so 0, +-1 and the octant values are exact).
+std::vector<float> twiddle_table(int n) {
+  std::vector<float> t(2 * static_cast<size_t>(n));
+  const int quarter = n / 4, eighth = n / 8;
+  for (int i = 0; i < n; ++i) {
+    const int qd = i / quarter;        // quadrant of the angle 2 pi i / N
+    const int rem = i - qd * quarter;  // position inside it
+    double c, s;                       // cos, sin of 2 pi rem / N
+    if (rem <= eighth) {
+      const double th = 2.0 * M_PI * rem / n;
+      c = std::cos(th);
+      s = std::sin(th);
+    } else {
+      const double th = 2.0 * M_PI * (quarter - rem) / n;
+      c = std::sin(th);
+      s = std::cos(th);
+    }
+    double ci, si;  // cos, sin of 2 pi i / N
+    switch (qd) {
+      case 0: ci = c; si = s; break;
+      case 1: ci = -s; si = c; break;
+      case 2: ci = -c; si = -s; break;
+      default: ci = s; si = -c; break;
+    }
+    t[2 * i] = static_cast<float>(ci);
+    t[2 * i + 1] = static_cast<float>(-si);
+  }
+  return t;
+}
+
+bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t ispl_abi_version(void) { return ISPL_ABI_VERSION; }
+
+const char* ispl_status_string(ispl_status s) {
+  switch (s) {
+    case ISPL_OK: return "ok";
+    case ISPL_ERR_INVALID_ARG: return "invalid argument";
+    case ISPL_ERR_UNSUPPORTED: return "unsupported";
+    case ISPL_ERR_OUT_OF_MEMORY: return "out of memory";
+    case ISPL_ERR_DEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* ispl_last_error(void) { return g_last_error.c_str(); }
+
+ispl_status ispl_plan(const ispl_config* cfg, int32_t n_pulses, int32_t* chunks,
+                      int32_t* waves_per_block, int32_t* blocks) {
+  const ispl_status st = validate_config(cfg);
+  if (st != ISPL_OK) return st;
+  if (n_pulses < 0 || n_pulses > cfg->max_pulses)
+    return fail(ISPL_ERR_INVALID_ARG, "n_pulses %d outside [0, max_pulses %d]", n_pulses,
+                cfg->max_pulses);
+  const Plan pl = make_plan(*cfg, n_pulses > 0 ? n_pulses : 1);
+  if (chunks) *chunks = n_pulses > 0 ? pl.chunks : 0;
+  if (waves_per_block) *waves_per_block = pl.rw;
+  if (blocks) *blocks = n_pulses > 0 ? static_cast<int32_t>(pl.blocks) : 0;
+  return ok();
+}
+
+ispl_status ispl_create(const ispl_config* cfg, ispl_ctx** out) {
+  if (!out) return fail(ISPL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  ispl_status st = validate_config(cfg);
+  if (st != ISPL_OK) return st;
+
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0)
+    return fail(ISPL_ERR_DEVICE, "no HIP device (%s)", hipGetErrorString(e));
+  if (cfg->device >= count)
+    return fail(ISPL_ERR_DEVICE, "device %d of %d", cfg->device, count);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, cfg->device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(ISPL_ERR_DEVICE, "device %d is %s; this library is built for gfx950",
+                cfg->device, prop.gcnArchName);
+
+  DeviceGuard guard(cfg->device);
+  ispl_ctx* ctx = new (std::nothrow) ispl_ctx{};
+  if (!ctx) return fail(ISPL_ERR_OUT_OF_MEMORY, "host allocation");
+  ctx->cfg = *cfg;
+  const Plan worst = make_plan(*cfg, cfg->max_pulses);
+
+  const std::vector<float> tw = twiddle_table(cfg->fft_len);
+  e = hipMalloc(reinterpret_cast<void**>(&ctx->twiddle), tw.size() * sizeof(float));
+  if (e != hipSuccess) {
+    delete ctx;
+    return fail(ISPL_ERR_OUT_OF_MEMORY, "twiddle table: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(ctx->twiddle, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(ctx->twiddle);
+    delete ctx;
+    return hip_fail(e, "twiddle upload");
+  }
+  // A plan's chunk count is its unclamped count capped at n_pulses, so the
+  // plan for max_pulses has the largest one and bounds the partial buffer.
+  const int32_t cmax = worst.chunks;
+  ctx->chunks_max = cmax;
+  if (cmax > 1) {
+    const size_t bytes = static_cast<size_t>(cmax) * cfg->n_gates * cfg->fft_len * sizeof(float);
+    e = hipMalloc(reinterpret_cast<void**>(&ctx->partial), bytes);
+    if (e != hipSuccess) {
+      (void)hipFree(ctx->twiddle);
+      delete ctx;
+      return fail(ISPL_ERR_OUT_OF_MEMORY, "chunk partials (%zu bytes): %s", bytes,
+                  hipGetErrorString(e));
+    }
+  }
+  *out = ctx;
+  return ok();
+}
+
+void ispl_destroy(ispl_ctx* ctx) {
+  if (!ctx) return;
+  {
+    DeviceGuard guard(ctx->cfg.device);
+    (void)hipDeviceSynchronize();
+    if (ctx->partial) (void)hipFree(ctx->partial);
+    if (ctx->twiddle) (void)hipFree(ctx->twiddle);
+  }
+  delete ctx;
+}
+
+ispl_status ispl_integrate_spectra(ispl_ctx* ctx, const void* samples, const float* tx_code,
+                                   int32_t tx_per_pulse, int32_t n_pulses, float* spectra,
+                                   int32_t accumulate, void* stream) {
+  if (!ctx) return fail(ISPL_ERR_INVALID_ARG, "context is NULL");
+  const ispl_config& c = ctx->cfg;
+  if (n_pulses < 0 || n_pulses > c.max_pulses)
+    return fail(ISPL_ERR_INVALID_ARG, "n_pulses %d outside [0, max_pulses %d]", n_pulses,
+                c.max_pulses);
+  if (!spectra) return fail(ISPL_ERR_INVALID_ARG, "spectra is NULL");
+  if (misaligned(spectra, 4)) return fail(ISPL_ERR_INVALID_ARG, "spectra not 4-byte aligned");
+  if (n_pulses > 0) {
+    if (!samples) return fail(ISPL_ERR_INVALID_ARG, "samples is NULL");
+    if (!tx_code) return fail(ISPL_ERR_INVALID_ARG, "tx_code is NULL");
+    const size_t sa = c.sample_type == ISPL_SAMPLES_CI16 ? 4 : 8;
+    if (misaligned(samples, sa))
+      return fail(ISPL_ERR_INVALID_ARG, "samples not %zu-byte aligned", sa);
+    if (misaligned(tx_code, 8)) return fail(ISPL_ERR_INVALID_ARG, "tx_code not 8-byte aligned");
+  }
+  if ((tx_per_pulse != 0 && tx_per_pulse != 1) || (accumulate != 0 && accumulate != 1))
+    return fail(ISPL_ERR_INVALID_ARG, "tx_per_pulse and accumulate must be 0 or 1");
+
+  DeviceGuard guard(c.device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t elems = static_cast<int64_t>(c.n_gates) * c.fft_len;
+  hipError_t e;
+  if (n_pulses == 0) {
+    if (!accumulate) {
+      e = ispl::launch_fill_zero(spectra, elems, s);
+      if (e != hipSuccess) return hip_fail(e, "fill_zero launch");
+    }
+    return ok();
+  }
+  const Plan pl = make_plan(c, n_pulses);
+  if (pl.chunks > ctx->chunks_max)
+    return fail(ISPL_ERR_INVALID_ARG, "internal: plan needs %d chunks > %d", pl.chunks,
+                ctx->chunks_max);
+
+  ispl::FusedArgs a{};
+  a.samples = samples;
+  a.tx = tx_code;
+  a.twiddle = ctx->twiddle;
+  a.out = pl.chunks == 1 ? spectra : ctx->partial;
+  a.stride = c.pulse_stride;
+  a.n_fft = c.fft_len;
+  a.log2_r = ilog2(c.fft_len / ispl::SUB);
+  a.code_len = c.code_len;
+  a.n_gates = c.n_gates;
+  a.gate_step = c.gate_step;
+  a.first_gate = c.first_gate;
+  a.n_pulses = n_pulses;
+  a.chunks = pl.chunks;
+  a.tx_per_pulse = tx_per_pulse;
+  a.accumulate = accumulate;
+  a.sample_type = c.sample_type;
+  a.waves_per_block = pl.rw;
+  e = ispl::launch_fused(a, s);
+  if (e != hipSuccess) return hip_fail(e, "fused launch");
+  if (pl.chunks > 1) {
+    e = ispl::launch_reduce_chunks(ctx->partial, spectra, elems, pl.chunks, accumulate, s);
+    if (e != hipSuccess) return hip_fail(e, "chunk reduce launch");
+  }
+  return ok();
+}
+
+ispl_status ispl_find_plasma_line(ispl_ctx* ctx, const float* spectra, int32_t bin_lo,
+                                  int32_t bin_hi, int32_t* peak_bin, float* peak_power,
+                                  void* stream) {
+  if (!ctx) return fail(ISPL_ERR_INVALID_ARG, "context is NULL");
+  const ispl_config& c = ctx->cfg;
+  if (!spectra || !peak_bin) return fail(ISPL_ERR_INVALID_ARG, "spectra or peak_bin is NULL");
+  if (misaligned(spectra, 4) || misaligned(peak_bin, 4) || misaligned(peak_power, 4))
+    return fail(ISPL_ERR_INVALID_ARG, "pointer not 4-byte aligned");
+  if (bin_lo < 0 || bin_lo >= c.fft_len || bin_hi < 1 || bin_hi > c.fft_len || bin_lo == bin_hi)
+    return fail(ISPL_ERR_INVALID_ARG, "band [%d, %d) invalid for fft_len %d", bin_lo, bin_hi,
+                c.fft_len);
+  DeviceGuard guard(c.device);
+  const hipError_t e = ispl::launch_peak(spectra, c.n_gates, c.fft_len, bin_lo, bin_hi,
+                                         peak_bin, peak_power, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "peak launch");
+  return ok();
+}
+
+}  // extern "C"

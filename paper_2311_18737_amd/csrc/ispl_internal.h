@@ -1,0 +1,51 @@
+// Internal interface between the C-ABI layer (ispl_api.cpp) and the device
+// code (ispl_kernels.hip).  Not installed, not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace ispl {
+
+// Points one wave transforms: the decoded row (L <= SUB samples) is turned
+// into R = N / SUB interleaved sub-spectra of SUB points each.
+constexpr int SUB = 1024;
+constexpr int MAX_WAVES_PER_BLOCK = 16;
+
+// Geometry and plan of one fused launch.
+struct FusedArgs {
+  const void* samples;     // [P][stride] ci16 or c64
+  const float* tx;         // complex64 pairs, [P][L] or [L]
+  const float* twiddle;    // complex64 pairs, W_N^i for i < N
+  float* out;              // S [G][N] when chunks == 1, else partials [C][G][N]
+  int64_t stride;          // samples per echo row
+  int32_t n_fft;           // N
+  int32_t log2_r;          // log2(N / SUB)
+  int32_t code_len;        // L
+  int32_t n_gates;         // G
+  int32_t gate_step;       // s
+  int32_t first_gate;      // g0
+  int32_t n_pulses;        // P
+  int32_t chunks;          // C
+  int32_t tx_per_pulse;    // 0 / 1
+  int32_t accumulate;      // only read when chunks == 1
+  int32_t sample_type;     // 0 c64, 1 ci16
+  int32_t waves_per_block; // RW in {1, 2, 4, 8, 16}
+};
+
+// Static LDS bytes of one fused workgroup with `rw` waves.
+int fused_lds_bytes(int rw);
+
+hipError_t launch_fused(const FusedArgs& a, hipStream_t stream);
+
+// S[g][k] = (accumulate ? S[g][k] : 0) + sum_{c < C} partial[c][g][k], c ascending.
+hipError_t launch_reduce_chunks(const float* partial, float* spectra, int64_t elems,
+                                int32_t chunks, int32_t accumulate, hipStream_t stream);
+
+hipError_t launch_fill_zero(float* dst, int64_t elems, hipStream_t stream);
+
+hipError_t launch_peak(const float* spectra, int32_t n_gates, int32_t n_fft, int32_t bin_lo,
+                       int32_t bin_hi, int32_t* peak_bin, float* peak_power,
+                       hipStream_t stream);
+
+}  // namespace ispl

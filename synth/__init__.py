@@ -16,5 +16,6 @@ from .echoes import (  # noqa: F401
     make_dataset,
     pulse_stride_for,
     quantise_ci16,
+    random_inputs,
     samples_needed,
 )

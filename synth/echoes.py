@@ -29,6 +29,8 @@ dataset is a pure function of its config and seed.
 from __future__ import annotations
 
 import dataclasses
+import hashlib
+import os
 from dataclasses import dataclass
 from typing import Optional
 
@@ -165,12 +167,47 @@ def draw_codes(cfg: EchoConfig, seed: int) -> np.ndarray:
     raise ValueError(f"unknown code_kind {cfg.code_kind!r}")
 
 
-def make_dataset(cfg: EchoConfig, seed: int = 0, progress=None) -> Dataset:
+def make_dataset(cfg: EchoConfig, seed: int = 0, progress=None,
+                 cache_dir: Optional[str] = None) -> Dataset:
     """Draw one seeded dataset for ``cfg``.
 
     ``progress``, if given, is called as progress(done_pulses, n_pulses) every
     100 pulses so long generations can report that they are alive.
+    ``cache_dir`` (default: $ISPL_SYNTH_CACHE, if set) keeps drawn datasets as
+    plain .npy files keyed by config and seed, so several processes in one
+    session draw a large workload once.
     """
+    if cache_dir is None:
+        cache_dir = os.environ.get("ISPL_SYNTH_CACHE") or None
+    if cache_dir is not None:
+        return _cached(cfg, seed, progress, cache_dir)
+    return _draw(cfg, seed, progress)
+
+
+def _cache_key(cfg: EchoConfig, seed: int) -> str:
+    text = repr(sorted(dataclasses.asdict(cfg).items())) + f"|seed={seed}|v1"
+    return hashlib.sha1(text.encode()).hexdigest()[:16]
+
+
+def _cached(cfg: EchoConfig, seed: int, progress, cache_dir: str) -> Dataset:
+    os.makedirs(cache_dir, exist_ok=True)
+    stem = os.path.join(cache_dir, f"{cfg.name}_{_cache_key(cfg, seed)}")
+    files = {k: f"{stem}_{k}.npy" for k in ("samples", "tx", "fline", "scalars")}
+    if all(os.path.exists(f) for f in files.values()):
+        sc = np.load(files["scalars"])
+        return Dataset(cfg=cfg, seed=seed, samples=np.load(files["samples"]),
+                       tx=np.load(files["tx"]), f_line_hz=np.load(files["fline"]),
+                       f_peak_hz=float(sc[0]), rho=float(sc[1]))
+    d = _draw(cfg, seed, progress)
+    for k, arr in (("samples", d.samples), ("tx", d.tx), ("fline", d.f_line_hz),
+                   ("scalars", np.array([d.f_peak_hz, d.rho]))):
+        tmp = files[k] + f".{os.getpid()}.tmp.npy"
+        np.save(tmp, arr)
+        os.replace(tmp, files[k])
+    return d
+
+
+def _draw(cfg: EchoConfig, seed: int, progress) -> Dataset:
     P, G, L = cfg.n_pulses, cfg.n_gates, cfg.code_len
     s, g0 = cfg.gate_step, cfg.first_gate
     stride = cfg.pulse_stride
@@ -231,3 +268,34 @@ def make_dataset(cfg: EchoConfig, seed: int = 0, progress=None) -> Dataset:
         raise ValueError(f"unknown sample_type {cfg.sample_type!r}")
     return Dataset(cfg=cfg, seed=seed, samples=samples, tx=tx, f_line_hz=f_line,
                    f_peak_hz=f_peak, rho=rho)
+
+
+def random_inputs(n_pulses: int, stride: int, code_len: int, *, sample_type: str = "c64",
+                  code_kind: str = "phase", tx_rows: Optional[int] = None, seed: int = 0,
+                  amplitude: float = 1.0):
+    """Unstructured seeded inputs for shape and edge-case tests.
+
+    Rows are complex Gaussian noise of rms ``amplitude`` (c64), or uniform int16
+    pairs in [-amplitude, amplitude] (ci16); codes are unit-modulus random
+    phases ("phase"), +-1 chips ("bpsk") or complex Gaussian ("gauss").
+    Returns (samples, tx) with tx shaped [tx_rows or n_pulses][code_len].
+    """
+    rng = np.random.default_rng([2311, 18737, 77, seed])
+    if sample_type == "c64":
+        x = (rng.standard_normal((n_pulses, stride)) + 1j * rng.standard_normal((n_pulses, stride)))
+        samples = (x * (amplitude / np.sqrt(2.0))).astype(np.complex64)
+    elif sample_type == "ci16":
+        a = int(min(amplitude, 32767))
+        samples = rng.integers(-a, a + 1, size=(n_pulses, stride, 2)).astype(np.int16)
+    else:
+        raise ValueError(sample_type)
+    rows = n_pulses if tx_rows is None else tx_rows
+    if code_kind == "phase":
+        tx = np.exp(1j * rng.uniform(0, 2 * np.pi, (rows, code_len)))
+    elif code_kind == "bpsk":
+        tx = rng.choice([-1.0, 1.0], size=(rows, code_len)) + 0j
+    elif code_kind == "gauss":
+        tx = rng.standard_normal((rows, code_len)) + 1j * rng.standard_normal((rows, code_len))
+    else:
+        raise ValueError(code_kind)
+    return samples, tx.astype(np.complex64)
