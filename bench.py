@@ -1,0 +1,238 @@
+"""Throughput of the plasma-line spectrum path on one MI355X.
+
+One step = the whole hot path over one batch already resident in HBM:
+ispl_integrate_spectra (decode, transform, |X|^2, pulse integration) on all
+pulses and gates, then ispl_find_plasma_line on the integrated spectra.
+
+Workload: 1000 pulses x 1000 range gates, code length 1000, FFT length 16384,
+raw complex int16 samples at 25 MHz (synthetic Chapman-layer echoes at -20 dB).
+Prints one JSON line.  Progress goes to stderr.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "range-gate spectra/s at N=16384 + % HBM roofline; learned-zoom vs plain speedup"
+WORKLOAD = "realistic"
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (published)
+PEAK_HBM_GBS = 8000.0      # MI355X HBM3E (published)
+KERNEL_SRC = os.path.join(ROOT, "paper_2311_18737_amd", "csrc", "ispl_kernels.hip")
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "fused_spectra_realistic_hbm_traffic.txt")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def flops_per_spectrum(n_fft: int, code_len: int) -> float:
+    """Algorithmic FP32 work of one pulse-gate spectrum: the conventional
+    5 N log2 N of a complex FFT, 4 N for |X|^2 and its accumulation, 6 L for
+    the complex decode multiply."""
+    return 5.0 * n_fft * math.log2(n_fft) + 4.0 * n_fft + 6.0 * code_len
+
+
+def algorithmic_bytes(cfg, bytes_per_sample: int) -> float:
+    """HBM bytes the path cannot avoid: every raw sample row and code read
+    once, the integrated spectrum written once."""
+    rows = cfg.n_pulses * cfg.pulse_stride * bytes_per_sample
+    codes = cfg.n_pulses * cfg.code_len * 8
+    spectra = cfg.n_gates * cfg.fft_len * 4
+    return float(rows + codes + spectra)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per fused launch from the committed rocprofv3 counter summary,
+    or None when it is absent or was taken on a different kernel source."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    text = open(PMC_SUMMARY).read()
+    m_hash = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]+)", text)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(d, cfg, budget_s: float):
+    """The FP64 oracle as it stands, timed on the host on a bounded sample:
+    whole gates (all pulses each) until the time budget is spent."""
+    from oracle import integrate_spectra
+
+    gates = []
+    t0 = time.perf_counter()
+    g = 0
+    while g < cfg.n_gates:
+        integrate_spectra(d.samples, d.tx, n_gates=cfg.n_gates, gate_step=cfg.gate_step,
+                          first_gate=cfg.first_gate, fft_len=cfg.fft_len, tx_per_pulse=True,
+                          gates=[g])
+        gates.append(g)
+        g += max(1, cfg.n_gates // 97)  # spread the sample over the range
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    spectra = len(gates) * cfg.n_pulses
+    return {
+        "value": spectra / dt,
+        "unit": "spectra/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{len(gates)} gates x {cfg.n_pulses} pulses of the workload "
+                  f"({spectra} pulse-gate spectra, {dt:.1f} s, float64 numpy, 1 thread)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of host time for the oracle baseline (0 = skip)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the spectrum "
+              "path is measured on one MI355X.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2311_18737_amd as ispl
+    from synth import CONFIGS, make_dataset
+
+    cfg = CONFIGS[WORKLOAD]
+    log(f"drawing {cfg.n_pulses} pulses x {cfg.n_gates} gates (seed {args.seed})")
+    d = make_dataset(cfg, args.seed, progress=lambda p, n: log(f"  {p}/{n} pulses"))
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    xs = torch.from_numpy(d.samples).to(dev)
+    xt = torch.from_numpy(d.tx).to(dev)
+    ctx = ispl.Context(code_len=cfg.code_len, fft_len=cfg.fft_len, n_gates=cfg.n_gates,
+                       gate_step=cfg.gate_step, first_gate=cfg.first_gate,
+                       pulse_stride=cfg.pulse_stride, sample_type=cfg.sample_type,
+                       max_pulses=cfg.n_pulses, device=0)
+    plan = ispl.plan(cfg.n_pulses, code_len=cfg.code_len, fft_len=cfg.fft_len,
+                     n_gates=cfg.n_gates, gate_step=cfg.gate_step, first_gate=cfg.first_gate,
+                     pulse_stride=cfg.pulse_stride, sample_type=cfg.sample_type,
+                     max_pulses=cfg.n_pulses)
+    S = torch.empty((cfg.n_gates, cfg.fft_len), dtype=torch.float32, device=dev)
+    bins = torch.empty(cfg.n_gates, dtype=torch.int32, device=dev)
+    power = torch.empty(cfg.n_gates, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.integrate_spectra(xs, xt, out=S, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        ctx.find_plasma_line(S, out_bins=bins, out_power=power, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    log(f"plan {plan}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    integ_ms = [e[0].elapsed_time(e[1]) for e in events]
+    peak_ms = [e[1].elapsed_time(e[2]) for e in events]
+    ms_per_step = wall * 1e3 / args.steps
+    log(f"step {ms_per_step:.3f} ms; integrate {np.mean(integ_ms):.3f} ms "
+        f"(min {np.min(integ_ms):.3f}, max {np.max(integ_ms):.3f}); peak {np.mean(peak_ms):.4f} ms")
+
+    if args.copy_calib_mib > 0:
+        n = args.copy_calib_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calib_mib} MiB done")
+
+    units = cfg.n_pulses * cfg.n_gates
+    t_kernel = float(np.mean(integ_ms)) / 1e3
+    flops = units * flops_per_spectrum(cfg.fft_len, cfg.code_len)
+    achieved_tflops = flops / t_kernel / 1e12
+    bps = 4 if cfg.sample_type == "ci16" else 8
+    alg_bytes = algorithmic_bytes(cfg, bps)
+    traffic = measured_traffic()
+
+    cpu = None
+    if args.cpu_budget > 0:
+        log(f"timing the oracle on the host ({args.cpu_budget:.0f} s budget)")
+        cpu = cpu_baseline(d, cfg, args.cpu_budget)
+
+    value = units / (ms_per_step / 1e3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spectra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "realistic: 1000 pulses x 1000 range gates, BPSK code length 1000, "
+                        "FFT N=16384, complex int16 samples at 25 MHz, Chapman layer, -20 dB, "
+                        "2 kHz line width",
+            "n_pulses": cfg.n_pulses, "n_gates": cfg.n_gates, "code_len": cfg.code_len,
+            "fft_len": cfg.fft_len, "gate_step": cfg.gate_step, "sample_type": cfg.sample_type,
+            "parallelism": "single GPU", "plan": plan,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved_tflops,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved_tflops / PEAK_FP32_TFLOPS,
+            "traffic": traffic,
+        },
+        "hbm": {
+            "algorithmic_bytes": alg_bytes,
+            "achieved_GBs": alg_bytes / t_kernel / 1e9,
+            "frac_of_8TBs": alg_bytes / t_kernel / 1e9 / PEAK_HBM_GBS,
+        },
+        "kernel_ms": {"integrate_mean": float(np.mean(integ_ms)),
+                      "integrate_min": float(np.min(integ_ms)),
+                      "peak_pick_mean": float(np.mean(peak_ms))},
+        "realtime_factor": (cfg.n_pulses * 10e-3) / (ms_per_step / 1e3),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
