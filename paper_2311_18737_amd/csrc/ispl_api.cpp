@@ -64,6 +64,11 @@ constexpr int kComputeUnits = 256;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kMaxWavesPerCu = 16;
 constexpr int kMaxChunks = 256;
+#ifndef ISPL_MAX_WAVES_PER_BLOCK  // build-time tuning knob (1, 2, 4, 8 or 16)
+#define ISPL_MAX_WAVES_PER_BLOCK 16
+#endif
+constexpr int kMaxWavesPerBlock = ISPL_MAX_WAVES_PER_BLOCK;
+static_assert(kMaxWavesPerBlock <= ispl::MAX_WAVES_PER_BLOCK, "at most 16 waves per block");
 constexpr int64_t kMaxPartialBytes = int64_t{1} << 30;
 
 struct Plan {
@@ -76,7 +81,7 @@ struct Plan {
 Plan make_plan(const ispl_config& c, int32_t n_pulses) {
   Plan pl{};
   const int r = c.fft_len / ispl::SUB;
-  pl.rw = r < ispl::MAX_WAVES_PER_BLOCK ? r : ispl::MAX_WAVES_PER_BLOCK;
+  pl.rw = r < kMaxWavesPerBlock ? r : kMaxWavesPerBlock;
   pl.zgroups = r / pl.rw;
   int per_cu = kLdsPerCu / ispl::fused_lds_bytes(pl.rw);
   if (per_cu * pl.rw > kMaxWavesPerCu) per_cu = kMaxWavesPerCu / pl.rw;
