@@ -68,6 +68,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch ships its own HIP runtime; load it first so that the library binds
+    # to the same runtime instance as the tensors whose pointers it receives.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(path):
         raise ImportError(
             f"HIP library {path} is missing: build it with "

@@ -13,12 +13,15 @@
 // so each bin class k1 is one pre-twiddled 1024-point DFT (the radix-R first
 // pass of the full transform is empty apart from its twiddles).  One wave owns
 // one k1 and computes its 1024-point DFT as 16 x 16 x 4:
-//   pass 1  lane l holds y[l + 64 j], j < 16: 16-point DFT over j, twiddle;
+//   pass 1  lane l holds y[l + 64 j], j < 16: pre-twiddle W_N^{64 k1 j},
+//           16-point DFT over j;
 //   pass 2  via an LDS transpose, lane ka + 16 r holds u_ka[r + 4 m]:
-//           16-point DFT over m;
+//           twiddle W_N^{(r + 4 m)(k1 + R ka)}, 16-point DFT over m;
 //   pass 3  the four 16-lane rows swap values in registers
 //           (v_permlane16/32_swap), then twiddle W_64^{r kc} and 4-point DFTs
 //           over r give bin kk = ka + 16 kc + 256 kd.
+// Every twiddle product is folded into the first butterfly layer that
+// follows it (a + w b and 2 a - (a + w b) as fused multiply-adds).
 // Every lane keeps the running |X|^2 of its 16 bins in registers across the
 // whole pulse loop, so the only spectrum traffic is one store per bin at the
 // end.  The waves of a workgroup share one gate and one pulse at a time: the
@@ -57,16 +60,52 @@ __device__ __forceinline__ float2 conj_mul(float2 c, float2 x) {  // conj(c) * x
   return make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
 }
 
+// a + w b, two fused multiply-adds per component.
+__device__ __forceinline__ float2 cmuladd(float2 a, float2 w, float2 b) {
+  return make_float2(fmaf(w.x, b.x, fmaf(-w.y, b.y, a.x)), fmaf(w.x, b.y, fmaf(w.y, b.x, a.y)));
+}
+
+// 2 a - s: with s = a + w b this is a - w b at one FMA per component.
+__device__ __forceinline__ float2 twice_minus(float2 a, float2 s) {
+  return make_float2(fmaf(2.f, a.x, -s.x), fmaf(2.f, a.y, -s.y));
+}
+
+// Second layer of a 4-point forward DFT from s02 = x0 + x2, d02 = x0 - x2,
+// s13 = x1 + x3, d13 = x1 - x3; outputs in natural order.
+__device__ __forceinline__ void dft4_tail(float2 s02, float2 d02, float2 s13, float2 d13,
+                                          float2& y0, float2& y1, float2& y2, float2& y3) {
+  y0 = make_float2(s02.x + s13.x, s02.y + s13.y);
+  y2 = make_float2(s02.x - s13.x, s02.y - s13.y);
+  y1 = make_float2(d02.x + d13.y, d02.y - d13.x);  // d02 - i d13
+  y3 = make_float2(d02.x - d13.y, d02.y + d13.x);  // d02 + i d13
+}
+
 // 4-point forward DFT in place, natural order in and out.
 __device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
-  const float t0x = a0.x + a2.x, t0y = a0.y + a2.y;
-  const float t1x = a0.x - a2.x, t1y = a0.y - a2.y;
-  const float t2x = a1.x + a3.x, t2y = a1.y + a3.y;
-  const float t3x = a1.x - a3.x, t3y = a1.y - a3.y;
-  a0 = make_float2(t0x + t2x, t0y + t2y);
-  a2 = make_float2(t0x - t2x, t0y - t2y);
-  a1 = make_float2(t1x + t3y, t1y - t3x);  // t1 - i t3
-  a3 = make_float2(t1x - t3y, t1y + t3x);  // t1 + i t3
+  const float2 s02 = make_float2(a0.x + a2.x, a0.y + a2.y);
+  const float2 d02 = make_float2(a0.x - a2.x, a0.y - a2.y);
+  const float2 s13 = make_float2(a1.x + a3.x, a1.y + a3.y);
+  const float2 d13 = make_float2(a1.x - a3.x, a1.y - a3.y);
+  dft4_tail(s02, d02, s13, d13, a0, a1, a2, a3);
+}
+
+// DFT4 of (a0, w1 a1, w2 a2, w3 a3): the twiddle products fold into the first
+// butterfly layer as multiply-adds (a + w b, then 2 a - (a + w b)).
+__device__ __forceinline__ void dft4_w123(float2& a0, float2& a1, float2& a2, float2& a3,
+                                          float2 w1, float2 w2, float2 w3) {
+  const float2 s02 = cmuladd(a0, w2, a2);
+  const float2 d02 = twice_minus(a0, s02);
+  const float2 p1 = cmul(a1, w1);
+  const float2 s13 = cmuladd(p1, w3, a3);
+  const float2 d13 = twice_minus(p1, s13);
+  dft4_tail(s02, d02, s13, d13, a0, a1, a2, a3);
+}
+
+// DFT4 of (w0 a0, w1 a1, w2 a2, w3 a3).
+__device__ __forceinline__ void dft4_w0123(float2& a0, float2& a1, float2& a2, float2& a3,
+                                           float2 w0, float2 w1, float2 w2, float2 w3) {
+  a0 = cmul(a0, w0);
+  dft4_w123(a0, a1, a2, a3, w1, w2, w3);
 }
 
 constexpr float kC8 = 0.923879532511286756f;  // cos(pi / 8)
@@ -82,33 +121,50 @@ __device__ __forceinline__ Dft16Consts dft16_consts() {
   return Dft16Consts{in_vgpr(kC8), in_vgpr(kS8), in_vgpr(kR2)};
 }
 
-// 16-point forward DFT in registers, natural order in and out:
-// j = j1 + 4 j2, k = k1 + 4 k2; DFT4 over j2, twiddle W_16^{j1 k1}, DFT4 over j1.
-// Twiddles W_16^m = exp(-2 pi i m / 16): m = 1, 3, 9 general, m = 2, 6 the
-// (1 - i) / sqrt(2) family, m = 4 a swap.
-__device__ __forceinline__ void dft16(float2 (&v)[16], const Dft16Consts& k) {
-  dft4(v[0], v[4], v[8], v[12]);
-  dft4(v[1], v[5], v[9], v[13]);
-  dft4(v[2], v[6], v[10], v[14]);
-  dft4(v[3], v[7], v[11], v[15]);
-  v[5] = cmul(v[5], make_float2(k.c8, -k.s8));    // W^1
-  v[9] = make_float2(k.r2 * (v[9].x + v[9].y), k.r2 * (v[9].y - v[9].x));  // W^2
-  v[13] = cmul(v[13], make_float2(k.s8, -k.c8));  // W^3
-  v[6] = make_float2(k.r2 * (v[6].x + v[6].y), k.r2 * (v[6].y - v[6].x));  // W^2
-  v[10] = make_float2(v[10].y, -v[10].x);         // W^4
-  v[14] = make_float2(k.r2 * (v[14].y - v[14].x), -k.r2 * (v[14].x + v[14].y));  // W^6
-  v[7] = cmul(v[7], make_float2(k.s8, -k.c8));    // W^3
-  v[11] = make_float2(k.r2 * (v[11].y - v[11].x), -k.r2 * (v[11].x + v[11].y));  // W^6
-  v[15] = cmul(v[15], make_float2(-k.c8, k.s8));  // W^9
-  dft4(v[0], v[1], v[2], v[3]);
-  dft4(v[4], v[5], v[6], v[7]);
-  dft4(v[8], v[9], v[10], v[11]);
-  dft4(v[12], v[13], v[14], v[15]);
+// Second stage of a 16-point DFT (j = j1 + 4 j2, k = k1 + 4 k2): after the
+// DFT4s over j2, v[j1 + 4 k1] holds a[j1][k1]; twiddle W_16^{j1 k1} and DFT4
+// over j1, then leave X[k] in v[k].  W_16^m = exp(-2 pi i m / 16).
+__device__ __forceinline__ void dft16_stage_b(float2 (&v)[16], const Dft16Consts& k) {
+  const float2 w1 = make_float2(k.c8, -k.s8), w2 = make_float2(k.r2, -k.r2);
+  const float2 w3 = make_float2(k.s8, -k.c8), w9 = make_float2(-k.c8, k.s8);
+  const float2 w6 = make_float2(-k.r2, -k.r2);
+  dft4(v[0], v[1], v[2], v[3]);                       // k1 = 0: W^0, W^0, W^0, W^0
+  dft4_w123(v[4], v[5], v[6], v[7], w1, w2, w3);      // k1 = 1: W^0, W^1, W^2, W^3
+  {                                                   // k1 = 2: W^0, W^2, W^4, W^6
+    const float2 a0 = v[8], a2 = v[10];
+    const float2 s02 = make_float2(a0.x + a2.y, a0.y - a2.x);  // a0 + (-i) a2
+    const float2 d02 = make_float2(a0.x - a2.y, a0.y + a2.x);
+    const float2 p1 = make_float2(k.r2 * (v[9].x + v[9].y), k.r2 * (v[9].y - v[9].x));
+    const float2 s13 = cmuladd(p1, w6, v[11]);
+    const float2 d13 = twice_minus(p1, s13);
+    dft4_tail(s02, d02, s13, d13, v[8], v[9], v[10], v[11]);
+  }
+  dft4_w123(v[12], v[13], v[14], v[15], w3, w6, w9);  // k1 = 3: W^0, W^3, W^6, W^9
+  // position 4 k1 + k2 holds X[k1 + 4 k2]
   float2 t[16];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) t[k] = v[4 * (k & 3) + (k >> 2)];
+  for (int i = 0; i < 16; ++i) t[i] = v[4 * (i & 3) + (i >> 2)];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) v[k] = t[k];
+  for (int i = 0; i < 16; ++i) v[i] = t[i];
+}
+
+// 16-point forward DFT of (w[j] v[j]) with w[0] = 1.
+__device__ __forceinline__ void dft16_pre1(float2 (&v)[16], const float2 (&w)[16],
+                                           const Dft16Consts& k) {
+  dft4_w123(v[0], v[4], v[8], v[12], w[4], w[8], w[12]);
+#pragma unroll
+  for (int j1 = 1; j1 < 4; ++j1)
+    dft4_w0123(v[j1], v[j1 + 4], v[j1 + 8], v[j1 + 12], w[j1], w[j1 + 4], w[j1 + 8], w[j1 + 12]);
+  dft16_stage_b(v, k);
+}
+
+// 16-point forward DFT of (w[j] v[j]).
+__device__ __forceinline__ void dft16_pre(float2 (&v)[16], const float2 (&w)[16],
+                                          const Dft16Consts& k) {
+#pragma unroll
+  for (int j1 = 0; j1 < 4; ++j1)
+    dft4_w0123(v[j1], v[j1 + 4], v[j1 + 8], v[j1 + 12], w[j1], w[j1 + 4], w[j1 + 8], w[j1 + 12]);
+  dft16_stage_b(v, k);
 }
 
 // Orders this wave's LDS accesses around a cross-lane exchange.  LDS requests
@@ -203,12 +259,12 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
 
   // Twiddles, fixed over the pulse loop.
   float2 pre[16];     // W_N^{64 k1 j}: same for every lane
-  float2 tw1[16];     // W_N^{l (k1 + R ka)} = W_N^{k1 l} W_1024^{l ka}
+  float2 tw2[16];     // W_N^{l (k1 + R ka)} for the pass-1 lane l = row + 4 m
   float2 tw3[4][3];   // W_64^{r kc}, r = 1..3, kc = 4 row + t (applied in pass 3)
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     pre[j] = tw[(64 * k1 * j) & nmask];
-    tw1[j] = tw[(lane * (k1 + R * j)) & nmask];
+    tw2[j] = tw[((row + 4 * j) * (k1 + R * ka)) & nmask];
   }
 #pragma unroll
   for (int t = 0; t < 4; ++t)
@@ -257,20 +313,16 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
     float2 v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = ys[buf][lane + 64 * j];
-    if (k1 != 0) {
+    dft16_pre1(v, pre, dk);  // pre-twiddle folded into the first butterflies
 #pragma unroll
-      for (int j = 1; j < 16; ++j) v[j] = cmul(v[j], pre[j]);
-    }
-    dft16(v, dk);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) xw[k * XPITCH + lane] = cmul(v[k], tw1[k]);
+    for (int k = 0; k < 16; ++k) xw[k * XPITCH + lane] = v[k];
     wave_lds_sync();
 
-    // pass 2: lane (ka, r) transforms u_ka[r + 4 m] over m, giving the
-    // partial bins v_{ka,r}[kc]
+    // pass 2: lane (ka, r) twiddles u_ka[r + 4 m] by W_N^{(r + 4 m)(k1 + R ka)}
+    // and transforms over m, giving the partial bins v_{ka,r}[kc]
 #pragma unroll
     for (int m = 0; m < 16; ++m) v[m] = xw[p2base + 4 * m];
-    dft16(v, dk);
+    dft16_pre(v, tw2, dk);
 
     // pass 3: the 4-point DFT over r runs across the four 16-lane rows.  For
     // each t a row transpose hands row g the four values v_{ka,r}[4 g + t],
@@ -281,11 +333,9 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
       float im[4] = {v[t].y, v[4 + t].y, v[8 + t].y, v[12 + t].y};
       row_transpose4(re);
       row_transpose4(im);
-      float2 c0 = make_float2(re[0], im[0]);
-      float2 c1 = cmul(make_float2(re[1], im[1]), tw3[t][0]);
-      float2 c2 = cmul(make_float2(re[2], im[2]), tw3[t][1]);
-      float2 c3 = cmul(make_float2(re[3], im[3]), tw3[t][2]);
-      dft4(c0, c1, c2, c3);
+      float2 c0 = make_float2(re[0], im[0]), c1 = make_float2(re[1], im[1]);
+      float2 c2 = make_float2(re[2], im[2]), c3 = make_float2(re[3], im[3]);
+      dft4_w123(c0, c1, c2, c3, tw3[t][0], tw3[t][1], tw3[t][2]);
       acc[4 * t + 0] = fmaf(c0.y, c0.y, fmaf(c0.x, c0.x, acc[4 * t + 0]));
       acc[4 * t + 1] = fmaf(c1.y, c1.y, fmaf(c1.x, c1.x, acc[4 * t + 1]));
       acc[4 * t + 2] = fmaf(c2.y, c2.y, fmaf(c2.x, c2.x, acc[4 * t + 2]));
