@@ -95,6 +95,62 @@ def cpu_baseline(d, cfg, budget_s: float):
     }
 
 
+# Section 4 / Table 1 of the paper: 100 pulses, 16384-sample codes, 4096 gates
+# with a step of 25, FFT length 16384; its best GPU (GTX 780 Ti) took 1.488 s,
+# including the per-row host-to-device copies.
+PAPER_TABLE1_BEST_S = 1.488
+
+
+def paper_workload(steps: int, seed: int, dev):
+    """Times the paper's own workload shape (integration + peak pick per run)."""
+    import numpy as np
+    import torch
+
+    import paper_2311_18737_amd as ispl
+    from synth import CONFIGS, make_dataset
+
+    cfg = CONFIGS["paper"]
+    log(f"paper workload: drawing {cfg.n_pulses} pulses x {cfg.n_gates} gates, L = N = 16384")
+    d = make_dataset(cfg, seed)
+    xs = torch.from_numpy(d.samples).to(dev)
+    xt = torch.from_numpy(d.tx).to(dev)
+    ctx = ispl.Context(code_len=cfg.code_len, fft_len=cfg.fft_len, n_gates=cfg.n_gates,
+                       gate_step=cfg.gate_step, first_gate=cfg.first_gate,
+                       pulse_stride=cfg.pulse_stride, sample_type=cfg.sample_type,
+                       max_pulses=cfg.n_pulses, device=0)
+    S = torch.empty((cfg.n_gates, cfg.fft_len), dtype=torch.float32, device=dev)
+    bins = torch.empty(cfg.n_gates, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    ctx.integrate_spectra(xs, xt, out=S, stream=stream)
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e in ev:
+        e[0].record(stream)
+        ctx.integrate_spectra(xs, xt, out=S, stream=stream)
+        e[1].record(stream)
+        ctx.find_plasma_line(S, out_bins=bins, want_power=False, stream=stream)
+        e[2].record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    integ = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    units = cfg.n_pulses * cfg.n_gates
+    log(f"paper workload: {wall * 1e3:.3f} ms per run, integrate {integ:.3f} ms")
+    ctx.close()
+    return {
+        "workload": "paper Section 4 shape: 100 pulses x 4096 gates, code length 16384, "
+                    "gate step 25, FFT N=16384, complex64 (synthetic)",
+        "ms_per_run": wall * 1e3,
+        "integrate_ms": integ,
+        "spectra_per_s": units / wall,
+        "realtime_factor": (cfg.n_pulses * 10e-3) / wall,
+        "paper_best_gpu": {"hardware": "GTX 780 Ti", "seconds": PAPER_TABLE1_BEST_S,
+                           "spectra_per_s": units / PAPER_TABLE1_BEST_S,
+                           "note": "Table 1; includes per-row host-to-device copies"},
+        "speedup_vs_paper_best_gpu": PAPER_TABLE1_BEST_S / wall,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +159,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of host time for the oracle baseline (0 = skip)")
+    ap.add_argument("--paper-steps", type=int, default=5,
+                    help="timed runs of the paper's Section 4 workload (0 = skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -184,6 +242,8 @@ def main():
     alg_bytes = algorithmic_bytes(cfg, bps)
     traffic = measured_traffic()
 
+    paper = paper_workload(args.paper_steps, args.seed, dev) if args.paper_steps > 0 else None
+
     cpu = None
     if args.cpu_budget > 0:
         log(f"timing the oracle on the host ({args.cpu_budget:.0f} s budget)")
@@ -228,6 +288,7 @@ def main():
                       "integrate_min": float(np.min(integ_ms)),
                       "peak_pick_mean": float(np.mean(peak_ms))},
         "realtime_factor": (cfg.n_pulses * 10e-3) / (ms_per_step / 1e3),
+        "paper_workload": paper,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -66,7 +66,8 @@ typedef struct {
   int32_t abi_version;  /* must be ISPL_ABI_VERSION */
   int32_t code_len;     /* L >= 1: transmit code length in samples */
   int32_t fft_len;      /* N: power of two, L <= N.  This build: 1024 <= N <= 65536
-                           and L <= 1024 (other valid shapes: ISPL_ERR_UNSUPPORTED) */
+                           with L <= 1024, or 16384 <= N <= 65536 with
+                           L <= 16384 (other valid shapes: ISPL_ERR_UNSUPPORTED) */
   int32_t n_gates;      /* G >= 1 range gates */
   int32_t gate_step;    /* s >= 1 samples between consecutive gate starts */
   int32_t first_gate;   /* g0 >= 0: echo sample where gate 0 starts */

@@ -72,18 +72,26 @@ static_assert(kMaxWavesPerBlock <= ispl::MAX_WAVES_PER_BLOCK, "at most 16 waves 
 constexpr int64_t kMaxPartialBytes = int64_t{1} << 30;
 
 struct Plan {
+  int sub_len;    // M: points of one sub-transform (1024, or 16384 for L > 1024)
+  int r;          // R = N / M sub-transforms (bin classes) per spectrum
   int rw;         // waves per workgroup
-  int zgroups;    // workgroups per gate and chunk (R / rw)
+  int zgroups;    // workgroups per gate and chunk
   int chunks;     // pulse chunks
   int64_t blocks; // workgroups of the fused launch
 };
 
 Plan make_plan(const ispl_config& c, int32_t n_pulses) {
   Plan pl{};
-  const int r = c.fft_len / ispl::SUB;
-  pl.rw = r < kMaxWavesPerBlock ? r : kMaxWavesPerBlock;
-  pl.zgroups = r / pl.rw;
-  int per_cu = kLdsPerCu / ispl::fused_lds_bytes(pl.rw);
+  pl.sub_len = c.code_len <= ispl::SUB ? ispl::SUB : 16 * ispl::SUB;
+  pl.r = c.fft_len / pl.sub_len;
+  if (pl.sub_len == ispl::SUB) {  // one wave per bin class
+    pl.rw = pl.r < kMaxWavesPerBlock ? pl.r : kMaxWavesPerBlock;
+    pl.zgroups = pl.r / pl.rw;
+  } else {                        // sixteen waves per bin class
+    pl.rw = 16;
+    pl.zgroups = pl.r;
+  }
+  int per_cu = kLdsPerCu / ispl::fused_lds_bytes(pl.rw, pl.sub_len);
   if (per_cu * pl.rw > kMaxWavesPerCu) per_cu = kMaxWavesPerCu / pl.rw;
   if (per_cu < 1) per_cu = 1;
   const int64_t slots = int64_t{kComputeUnits} * per_cu;
@@ -127,9 +135,12 @@ ispl_status validate_config(const ispl_config* c) {
   // what this build implements
   if (c->fft_len < ispl::SUB || c->fft_len > 65536)
     return fail(ISPL_ERR_UNSUPPORTED, "fft_len %d outside [1024, 65536]", c->fft_len);
-  if (c->code_len > ispl::SUB)
-    return fail(ISPL_ERR_UNSUPPORTED, "code_len %d > 1024", c->code_len);
-  // one 64-lane wave per (gate, bin class); keep the launch under 2^31 threads
+  if (c->code_len > 16 * ispl::SUB)
+    return fail(ISPL_ERR_UNSUPPORTED, "code_len %d > 16384", c->code_len);
+  if (c->code_len > ispl::SUB && c->fft_len < 16 * ispl::SUB)
+    return fail(ISPL_ERR_UNSUPPORTED, "code_len %d > 1024 needs fft_len >= 16384",
+                c->code_len);
+  // 64 lanes per (gate, bin class of 1024 points); keep a launch under 2^31 threads
   if (static_cast<int64_t>(c->n_gates) * (c->fft_len / ispl::SUB) * 64 >= (int64_t{1} << 31))
     return fail(ISPL_ERR_UNSUPPORTED, "n_gates %d too large for one launch", c->n_gates);
   return ISPL_OK;
@@ -323,7 +334,8 @@ ispl_status ispl_integrate_spectra(ispl_ctx* ctx, const void* samples, const flo
   a.out = pl.chunks == 1 ? spectra : ctx->partial;
   a.stride = c.pulse_stride;
   a.n_fft = c.fft_len;
-  a.log2_r = ilog2(c.fft_len / ispl::SUB);
+  a.sub_len = pl.sub_len;
+  a.log2_r = ilog2(pl.r);
   a.code_len = c.code_len;
   a.n_gates = c.n_gates;
   a.gate_step = c.gate_step;

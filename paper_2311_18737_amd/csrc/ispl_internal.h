@@ -7,8 +7,10 @@
 
 namespace ispl {
 
-// Points one wave transforms: the decoded row (L <= SUB samples) is turned
-// into R = N / SUB interleaved sub-spectra of SUB points each.
+// Points one wave transforms.  A decoded row of L samples is zero-padded to
+// N = R * M and split into R interleaved sub-spectra of M points each, with
+// M = SUB (L <= 1024, one wave per sub-transform) or M = 16 SUB
+// (1024 < L <= 16384, sixteen waves per sub-transform).
 constexpr int SUB = 1024;
 constexpr int MAX_WAVES_PER_BLOCK = 16;
 
@@ -20,7 +22,8 @@ struct FusedArgs {
   float* out;              // S [G][N] when chunks == 1, else partials [C][G][N]
   int64_t stride;          // samples per echo row
   int32_t n_fft;           // N
-  int32_t log2_r;          // log2(N / SUB)
+  int32_t sub_len;         // M: SUB or 16 * SUB
+  int32_t log2_r;          // log2(N / M)
   int32_t code_len;        // L
   int32_t n_gates;         // G
   int32_t gate_step;       // s
@@ -30,11 +33,11 @@ struct FusedArgs {
   int32_t tx_per_pulse;    // 0 / 1
   int32_t accumulate;      // only read when chunks == 1
   int32_t sample_type;     // 0 c64, 1 ci16
-  int32_t waves_per_block; // RW in {1, 2, 4, 8, 16}
+  int32_t waves_per_block; // RW in {1, 2, 4, 8, 16} (16 when M = 16 SUB)
 };
 
-// Static LDS bytes of one fused workgroup with `rw` waves.
-int fused_lds_bytes(int rw);
+// Static LDS bytes of one fused workgroup with `rw` waves and sub-transform M.
+int fused_lds_bytes(int rw, int sub_len);
 
 hipError_t launch_fused(const FusedArgs& a, hipStream_t stream);
 

@@ -217,6 +217,91 @@ struct SampleIO<1> {  // int16 (re, im) pairs; int16 -> float is exact
   }
 };
 
+// Twiddles of one wave's 1024-point transform of bin class kappa: the wave
+// produces bins kappa + S kb (S = N / 1024, kb < 1024) of the N-point
+// spectrum, so its input carries the factor W_N^{kappa n} on top of the
+// 1024-point DFT kernel W_N^{S kb n}.  Fixed over the pulse loop.
+struct WaveTwiddles {
+  float2 pre[16];    // pass 1: W_N^{64 kappa j}, the same for every lane
+  float2 tw2[16];    // pass 2: W_N^{l (kappa + S ka)} for the pass-1 lane l = row + 4 m
+  float2 tw3[4][3];  // pass 3: W_64^{r kc}, r = 1..3, kc = 4 row + t
+};
+
+__device__ __forceinline__ void load_wave_twiddles(WaveTwiddles& w, const float2* __restrict__ tw,
+                                                   int n_fft, int kappa, int lane) {
+  const int nmask = n_fft - 1, S = n_fft >> 10;
+  const int ka = lane & 15, row = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    w.pre[j] = tw[(64 * kappa * j) & nmask];
+    w.tw2[j] = tw[((row + 4 * j) * (kappa + S * ka)) & nmask];
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 1; r < 4; ++r) w.tw3[t][r - 1] = tw[((n_fft >> 6) * r * (4 * row + t)) & nmask];
+}
+
+// One wave's 1024-point transform and power accumulation.  On entry lane l
+// holds f[l + 64 j] in v[j]; xw is the wave's exchange buffer.  On exit
+// acc[4 t + kd] += |F[kb]|^2 for kb = ka + 16 (4 row + t) + 256 kd, with
+// ka = lane & 15, row = lane >> 4 (F including the bin-class factors).
+__device__ __forceinline__ void wave_fft_accumulate(float2 (&v)[16], float2* xw,
+                                                    const WaveTwiddles& w,
+                                                    const Dft16Consts& dk, float (&acc)[16],
+                                                    int lane) {
+  const int ka = lane & 15, row = lane >> 4;
+  // pass 1: pre-twiddle and 16-point DFT over the stride-64 samples of a lane
+  dft16_pre1(v, w.pre, dk);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) xw[k * XPITCH + lane] = v[k];
+  wave_lds_sync();
+
+  // pass 2: lane (ka, r) twiddles u_ka[r + 4 m] and transforms over m, giving
+  // the partial bins v_{ka,r}[kc]
+  const int p2base = ka * XPITCH + row;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = xw[p2base + 4 * m];
+  dft16_pre(v, w.tw2, dk);
+
+  // pass 3: the 4-point DFT over r runs across the four 16-lane rows.  For
+  // each t a row transpose hands row g the four values v_{ka,r}[4 g + t],
+  // r = 0..3; then twiddle W_64^{r kc}, DFT over r, |X|^2 into the sums.
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    float re[4] = {v[t].x, v[4 + t].x, v[8 + t].x, v[12 + t].x};
+    float im[4] = {v[t].y, v[4 + t].y, v[8 + t].y, v[12 + t].y};
+    row_transpose4(re);
+    row_transpose4(im);
+    float2 c0 = make_float2(re[0], im[0]), c1 = make_float2(re[1], im[1]);
+    float2 c2 = make_float2(re[2], im[2]), c3 = make_float2(re[3], im[3]);
+    dft4_w123(c0, c1, c2, c3, w.tw3[t][0], w.tw3[t][1], w.tw3[t][2]);
+    acc[4 * t + 0] = fmaf(c0.y, c0.y, fmaf(c0.x, c0.x, acc[4 * t + 0]));
+    acc[4 * t + 1] = fmaf(c1.y, c1.y, fmaf(c1.x, c1.x, acc[4 * t + 1]));
+    acc[4 * t + 2] = fmaf(c2.y, c2.y, fmaf(c2.x, c2.x, acc[4 * t + 2]));
+    acc[4 * t + 3] = fmaf(c3.y, c3.y, fmaf(c3.x, c3.x, acc[4 * t + 3]));
+  }
+  (void)row;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
+// XCD runs a contiguous range of (gate, bin group, chunk) work items and
+// neighbouring gates, whose windows overlap, share that XCD's L2.
+__device__ __forceinline__ int xcd_block_id() {
+  const int nblk = gridDim.x;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int per = nblk >> 3, extra = nblk & 7;
+  return xcd < extra ? xcd * (per + 1) + slot : extra * (per + 1) + (xcd - extra) * per + slot;
+}
+
+// Output row of gate g (chunk c when the pulses are split).
+__device__ __forceinline__ float* out_row(const FusedArgs& a, int g, int c) {
+  return a.out + (a.chunks == 1 ? static_cast<int64_t>(g) * a.n_fft
+                                : (static_cast<int64_t>(c) * a.n_gates + g) * a.n_fft);
+}
+
+// Code lengths L <= 1024: one wave per bin class k1 (sub-transform length 1024).
+// RW waves share a gate and a pulse: the decoded row is staged once in LDS.
 template <int RW, int ST>
 __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   constexpr int NT = 64 * RW;
@@ -233,43 +318,20 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int R = 1 << a.log2_r;
   const int zgroups = R / RW;
-
-  // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
-  // XCD runs a contiguous range of (gate, bin group, chunk) work items and
-  // neighbouring gates, whose windows overlap, share that XCD's L2.
-  const int nblk = gridDim.x;
-  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
-  const int per = nblk >> 3, extra = nblk & 7;
-  int bid = xcd < extra ? xcd * (per + 1) + slot : extra * (per + 1) + (xcd - extra) * per + slot;
+  int bid = xcd_block_id();
   const int c = bid % a.chunks;
   bid /= a.chunks;
   const int zg = bid % zgroups;
   const int g = bid / zgroups;
   const int k1 = zg * RW + wave;
-  const int N = a.n_fft;
-  const int nmask = N - 1;
   const int L = a.code_len;
   const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
 
   const int p0 = static_cast<int>((static_cast<int64_t>(c) * a.n_pulses) / a.chunks);
   const int p1 = static_cast<int>((static_cast<int64_t>(c + 1) * a.n_pulses) / a.chunks);
 
-  // Lane roles after pass 1: lane = ka + 16 r, i.e. 16-lane row r, column ka.
-  const int ka = lane & 15, row = lane >> 4;
-
-  // Twiddles, fixed over the pulse loop.
-  float2 pre[16];     // W_N^{64 k1 j}: same for every lane
-  float2 tw2[16];     // W_N^{l (k1 + R ka)} for the pass-1 lane l = row + 4 m
-  float2 tw3[4][3];   // W_64^{r kc}, r = 1..3, kc = 4 row + t (applied in pass 3)
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    pre[j] = tw[(64 * k1 * j) & nmask];
-    tw2[j] = tw[((row + 4 * j) * (k1 + R * ka)) & nmask];
-  }
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int r = 1; r < 4; ++r) tw3[t][r - 1] = tw[((N >> 6) * r * (4 * row + t)) & nmask];
+  WaveTwiddles wt;
+  load_wave_twiddles(wt, tw, a.n_fft, k1, lane);
   const Dft16Consts dk = dft16_consts();
 
   float acc[16];
@@ -282,13 +344,13 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   raw_t raw[E];
   float2 cod[E];
   auto load = [&](int p) {
-    const int64_t row = static_cast<int64_t>(p) * a.stride + gate_off;
+    const int64_t rowp = static_cast<int64_t>(p) * a.stride + gate_off;
     const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int n = tid + i * NT;
       if (n < L) {
-        raw[i] = IO::load(a.samples, row + n);
+        raw[i] = IO::load(a.samples, rowp + n);
         cod[i] = txp[n];
       } else {
         raw[i] = IO::zero();
@@ -298,8 +360,6 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   };
 
   float2* xw = xs + wave * XWAVE;
-  const int p2base = ka * XPITCH + row;  // pass-2 entries: column row + 4 m of row ka
-
   if (p0 < p1) load(p0);
   for (int p = p0; p < p1; ++p) {
     const int buf = DBUF ? ((p - p0) & 1) : 0;
@@ -308,58 +368,110 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
     for (int i = 0; i < E; ++i) ys[buf][tid + i * NT] = conj_mul(cod[i], IO::cvt(raw[i]));
     if (p + 1 < p1) load(p + 1);
     __syncthreads();
-
-    // pass 1: 16-point DFTs over the stride-64 samples of each lane
     float2 v[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = ys[buf][lane + 64 * j];
-    dft16_pre1(v, pre, dk);  // pre-twiddle folded into the first butterflies
-#pragma unroll
-    for (int k = 0; k < 16; ++k) xw[k * XPITCH + lane] = v[k];
-    wave_lds_sync();
-
-    // pass 2: lane (ka, r) twiddles u_ka[r + 4 m] by W_N^{(r + 4 m)(k1 + R ka)}
-    // and transforms over m, giving the partial bins v_{ka,r}[kc]
-#pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = xw[p2base + 4 * m];
-    dft16_pre(v, tw2, dk);
-
-    // pass 3: the 4-point DFT over r runs across the four 16-lane rows.  For
-    // each t a row transpose hands row g the four values v_{ka,r}[4 g + t],
-    // r = 0..3; then twiddle W_64^{r kc}, DFT over r, |X|^2 into the sums.
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      float re[4] = {v[t].x, v[4 + t].x, v[8 + t].x, v[12 + t].x};
-      float im[4] = {v[t].y, v[4 + t].y, v[8 + t].y, v[12 + t].y};
-      row_transpose4(re);
-      row_transpose4(im);
-      float2 c0 = make_float2(re[0], im[0]), c1 = make_float2(re[1], im[1]);
-      float2 c2 = make_float2(re[2], im[2]), c3 = make_float2(re[3], im[3]);
-      dft4_w123(c0, c1, c2, c3, tw3[t][0], tw3[t][1], tw3[t][2]);
-      acc[4 * t + 0] = fmaf(c0.y, c0.y, fmaf(c0.x, c0.x, acc[4 * t + 0]));
-      acc[4 * t + 1] = fmaf(c1.y, c1.y, fmaf(c1.x, c1.x, acc[4 * t + 1]));
-      acc[4 * t + 2] = fmaf(c2.y, c2.y, fmaf(c2.x, c2.x, acc[4 * t + 2]));
-      acc[4 * t + 3] = fmaf(c3.y, c3.y, fmaf(c3.x, c3.x, acc[4 * t + 3]));
-    }
+    wave_fft_accumulate(v, xw, wt, dk, acc, lane);
   }
 
-  // Stage the sums through LDS in bin order, then store runs of RW
-  // consecutive bins (the whole row when one workgroup owns the gate).
-  // acc[4 t + kd] is bin k1 + R kk with kk = ka + 16 (4 row + t) + 256 kd.
+  // Stage the sums through LDS in bin order (bin k1 + R kb, k1 = zg RW + wave),
+  // then store runs of RW consecutive bins (the whole row when one workgroup
+  // owns the gate).
   __syncthreads();
   float* st = reinterpret_cast<float*>(xs);
+  const int ka = lane & 15, row = lane >> 4;
 #pragma unroll
   for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int kd = 0; kd < 4; ++kd)
       st[(ka + 16 * (4 * row + t) + 256 * kd) * RW + wave] = acc[4 * t + kd];
   __syncthreads();
-  float* out = a.out + (a.chunks == 1 ? static_cast<int64_t>(g) * N
-                                      : (static_cast<int64_t>(c) * a.n_gates + g) * N);
+  float* out = out_row(a, g, c);
   const bool add = (a.chunks == 1) && a.accumulate;
   for (int e = tid; e < RW * SUB; e += NT) {
-    const int kk = e / RW, w = e % RW;
-    float* dst = out + zg * RW + w + R * kk;
+    float* dst = out + zg * RW + e % RW + R * (e / RW);
+    *dst = add ? (*dst + st[e]) : st[e];
+  }
+}
+
+// Code lengths 1024 < L <= 16384: the 16 waves of a workgroup share one
+// 16384-point sub-transform (bin class k1 of N = R * 16384).  With
+// n = lg + 1024 j and kk = ka + 16 kb, thread lg = tid first does the 16-point
+// DFT over j (pre-twiddled by W_N^{1024 k1 j}); an all-to-all exchange through
+// LDS then hands wave ka the values U_ka[lg], whose 1024-point transform, with
+// the bin-class factor W_N^{lg (k1 + R ka)}, is bins k1 + R (ka + 16 kb).
+template <int ST>
+__global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
+  using IO = SampleIO<ST>;
+  __shared__ float2 xs[16 * XWAVE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int R = 1 << a.log2_r;  // N / 16384
+  int bid = xcd_block_id();
+  const int c = bid % a.chunks;
+  bid /= a.chunks;
+  const int k1 = bid % R;
+  const int g = bid / R;
+  const int N = a.n_fft;
+  const int L = a.code_len;
+  const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
+
+  const int p0 = static_cast<int>((static_cast<int64_t>(c) * a.n_pulses) / a.chunks);
+  const int p1 = static_cast<int>((static_cast<int64_t>(c + 1) * a.n_pulses) / a.chunks);
+
+  float2 xpre[16];  // W_N^{1024 k1 j}: same for every thread
+#pragma unroll
+  for (int j = 0; j < 16; ++j) xpre[j] = tw[(1024 * k1 * j) & (N - 1)];
+  WaveTwiddles wt;
+  load_wave_twiddles(wt, tw, N, k1 + R * wave, lane);
+  const Dft16Consts dk = dft16_consts();
+
+  float acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+
+  const int64_t gate_off = static_cast<int64_t>(a.first_gate) + static_cast<int64_t>(g) * a.gate_step;
+  const float2* __restrict__ txb = reinterpret_cast<const float2*>(a.tx);
+  float2* xw = xs + wave * XWAVE;
+
+  for (int p = p0; p < p1; ++p) {
+    const int64_t rowp = static_cast<int64_t>(p) * a.stride + gate_off;
+    const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0);
+    float2 v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int n = tid + 1024 * j;
+      v[j] = n < L ? conj_mul(txp[n], IO::cvt(IO::load(a.samples, rowp + n)))
+                   : make_float2(0.f, 0.f);
+    }
+    dft16_pre1(v, xpre, dk);
+    __syncthreads();  // every wave has finished its exchanges of the previous pulse
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xs[k * XWAVE + tid] = v[k];  // region k: U_k[lg]
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = xw[lane + 64 * j];    // U_wave[lane + 64 j]
+    wave_lds_sync();  // read before this wave reuses its region for its own exchange
+    wave_fft_accumulate(v, xw, wt, dk, acc, lane);
+  }
+
+  // acc[4 t + kd] is bin k1 + R kk with kk = wave + 16 kb,
+  // kb = ka + 16 (4 row + t) + 256 kd.
+  __syncthreads();
+  float* st = reinterpret_cast<float*>(xs);
+  const int ka = lane & 15, row = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int kd = 0; kd < 4; ++kd)
+      st[wave + 16 * (ka + 16 * (4 * row + t) + 256 * kd)] = acc[4 * t + kd];
+  __syncthreads();
+  float* out = out_row(a, g, c);
+  const bool add = (a.chunks == 1) && a.accumulate;
+  for (int e = tid; e < 16 * SUB; e += 1024) {
+    float* dst = out + k1 + R * e;
     *dst = add ? (*dst + st[e]) : st[e];
   }
 }
@@ -447,7 +559,16 @@ hipError_t launch_fused_t(const FusedArgs& a, hipStream_t stream) {
 }
 
 template <int ST>
+hipError_t launch_fused_long_t(const FusedArgs& a, hipStream_t stream) {
+  const int64_t blocks = static_cast<int64_t>(a.n_gates) * (1 << a.log2_r) * a.chunks;
+  hipLaunchKernelGGL((fused_spectra_long<ST>), dim3(static_cast<unsigned>(blocks)), dim3(1024), 0,
+                     stream, a);
+  return hipGetLastError();
+}
+
+template <int ST>
 hipError_t launch_fused_st(const FusedArgs& a, hipStream_t stream) {
+  if (a.sub_len == 16 * SUB) return launch_fused_long_t<ST>(a, stream);
   switch (a.waves_per_block) {
     case 1: return launch_fused_t<1, ST>(a, stream);
     case 2: return launch_fused_t<2, ST>(a, stream);
@@ -467,7 +588,8 @@ unsigned grid_for(int64_t elems) {
 
 }  // namespace
 
-int fused_lds_bytes(int rw) {
+int fused_lds_bytes(int rw, int sub_len) {
+  if (sub_len == 16 * SUB) return static_cast<int>(sizeof(float2)) * 16 * XWAVE;
   return static_cast<int>(sizeof(float2)) * (rw * XWAVE + (rw == 16 ? 2 : 1) * SUB);
 }
 

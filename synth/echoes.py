@@ -15,6 +15,9 @@ plasma line, so for pulse p and range r with start sample t_r = g0 + r*s:
     c_p[n]   = +-1 (BPSK) or exp(i phi) with phi uniform (unit-modulus code)
     f_{p,r}  = f_line(r) + delta_{p,r},  delta ~ N(0, (w / 2.3548)**2)
 
+(with ``echo_stride`` q > 1 only every q-th range cell echoes, which keeps
+drawing workloads with long codes and thousands of gates cheap).
+
 f_line(r) follows an alpha-Chapman electron-density layer: the plasma
 frequency scales with the square root of density, so
 f_line = f_peak * exp((1 - z - exp(-z)) / 4) with z = (h - 300 km) / 50 km,
@@ -67,6 +70,7 @@ class EchoConfig:
     code_kind: str = "bpsk"  # "bpsk" or "phase"
     tx_per_pulse: bool = True
     stride_align: int = 64
+    echo_stride: int = 1  # only ranges r with r % echo_stride == 0 carry a line
 
     def replace(self, **kw) -> "EchoConfig":
         return dataclasses.replace(self, **kw)
@@ -102,7 +106,8 @@ CONFIGS = {
         line_width_hz=2e3),
     "paper": EchoConfig(
         name="paper", cfg_id=6, n_pulses=100, n_gates=4096, code_len=16384,
-        fft_len=16384, sample_type="c64", f_peak_hz=(6e6, 6e6), snr_db=-10.0),
+        fft_len=16384, sample_type="c64", f_peak_hz=(6e6, 6e6), snr_db=-10.0,
+        echo_stride=64),
 }
 
 
@@ -232,10 +237,12 @@ def _draw(cfg: EchoConfig, seed: int, progress) -> Dataset:
 
     x_all = np.empty((P, stride), dtype=np.complex64)
     blocks = np.empty((n_blocks_row, s), dtype=np.complex64)
+    echo_r = np.arange(0, G, max(1, cfg.echo_stride))
     for p in range(P):
         c = tx[p if cfg.tx_per_pulse else 0]
         a = (rng_a.standard_normal(G) + 1j * rng_a.standard_normal(G)) * np.sqrt(rho / 2.0)
         f = f_line + (rng_j.standard_normal(G) * sig_w if sig_w > 0 else 0.0)
+        a, f = a[echo_r], np.broadcast_to(f, (G,))[echo_r]
         # phase in cycles, reduced to [0, 1) in float64 before the float32 trig call
         cyc = np.outer(f / cfg.fs_hz, n_axis)
         cyc -= np.floor(cyc)
@@ -248,8 +255,12 @@ def _draw(cfg: EchoConfig, seed: int, progress) -> Dataset:
         e[:, L:] = 0.0
         e[:, :L] *= c[None, :]
         blocks[...] = 0.0
-        for b in range(nb):
-            blocks[b:b + G, :] += e[:, b * s:(b + 1) * s]
+        if len(echo_r) == G:
+            for b in range(nb):
+                blocks[b:b + G, :] += e[:, b * s:(b + 1) * s]
+        else:
+            for b in range(nb):
+                blocks[b + echo_r, :] += e[:, b * s:(b + 1) * s]
         row = blocks.reshape(-1)[: stride - g0]
         noise = np.empty(stride, dtype=np.complex64)
         noise.real = rng_n.standard_normal(stride, dtype=np.float32)

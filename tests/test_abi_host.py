@@ -80,9 +80,18 @@ def test_config_validation(ispl_lib, field, value, status):
     assert h.value is None
 
 
-def test_unsupported_long_code(ispl_lib):
-    c = cfg(code_len=2000, fft_len=32768, pulse_stride=999 * 25 + 2000)
-    assert plan(ispl_lib, c, 10)[0] == _lib.ISPL_ERR_UNSUPPORTED
+def test_long_code_shapes(ispl_lib):
+    # 1024 < L <= 16384 runs as 16-wave sub-transforms of 16384 points
+    ok_cfg = cfg(code_len=2000, fft_len=32768, pulse_stride=999 * 25 + 2000)
+    st, ch, w, b = plan(ispl_lib, ok_cfg, 500)
+    assert (st, ch, w, b) == (0, 1, 16, 2000)
+    paper = cfg(code_len=16384, fft_len=16384, n_gates=4096, pulse_stride=250000,
+                sample_type=0, max_pulses=100)
+    assert plan(ispl_lib, paper, 100)[:3] == (0, 1, 16)
+    # not implemented: long codes with short FFTs, codes above 16384
+    for L, N in [(2000, 8192), (1025, 4096), (16385, 32768)]:
+        c = cfg(code_len=L, fft_len=N, pulse_stride=999 * 25 + L)
+        assert plan(ispl_lib, c, 10)[0] == _lib.ISPL_ERR_UNSUPPORTED, (L, N)
 
 
 def test_plans_of_named_workloads(ispl_lib):

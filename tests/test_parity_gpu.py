@@ -70,6 +70,11 @@ SHAPES = [
     (16384, 1023, 3, 2, 400, 1, "c64", True, "gauss"),
     (32768, 1024, 3, 5, 25, 0, "c64", True, "phase"),
     (65536, 500, 2, 3, 25, 7, "ci16", True, "bpsk"),
+    # long codes: sixteen waves per 16384-point sub-transform
+    (16384, 16384, 3, 3, 25, 0, "c64", True, "phase"),
+    (16384, 1025, 2, 3, 7, 0, "c64", False, "gauss"),
+    (32768, 2000, 3, 4, 25, 5, "ci16", True, "bpsk"),
+    (65536, 4000, 2, 2, 100, 3, "ci16", True, "phase"),
 ]
 
 
@@ -255,4 +260,35 @@ def test_realistic_workload_full_size(ispl):
     off = np.abs(((bins - truth + N // 2) % N) - N // 2)
     say(f"  line within 2 bins of truth on {np.mean(off <= 2):.4f} of gates")
     assert np.mean(off <= 2) >= 0.95
+    ctx.close()
+
+
+def test_paper_workload_full_size(ispl):
+    """The paper's own Section 4 shape (100 pulses x 4096 gates, L = N = 16384,
+    gate step 25): sampled gates against the oracle and Parseval on all gates."""
+    cfg = CONFIGS["paper"]
+    say("case paper workload: drawing 100 pulses")
+    d = make_dataset(cfg, 0)
+    G, N, L, s = cfg.n_gates, cfg.fft_len, cfg.code_len, cfg.gate_step
+    ctx, out, xs, xt = gpu_spectra(ispl, d.samples, d.tx, L=L, N=N, G=G, s=s, g0=0,
+                                   stride=cfg.pulse_stride, st="c64", max_pulses=cfg.n_pulses)
+    bins, _ = ctx.find_plasma_line(out)
+    torch.cuda.synchronize()
+    S = out.cpu().numpy()
+    bins = bins.cpu().numpy()
+    gates = [0, 1, 64, 2047, 4032, 4095]
+    ref = oracle_spectra(d.samples, d.tx, n_gates=G, gate_step=s, first_gate=0, fft_len=N,
+                         tx_per_pulse=True, gates=gates)
+    err = assert_spectra_match(S[gates], ref, what="paper sampled gates")
+    say(f"  {err}")
+    ref_bins, _ = oracle_peak(ref, 0, N)
+    check_peaks(bins[gates], ref, ref_bins)
+    x = d.samples.astype(np.complex128)
+    e = np.abs(x) ** 2
+    cs = np.concatenate([np.zeros((e.shape[0], 1)), np.cumsum(e, axis=1)], axis=1)
+    starts = np.arange(G) * s
+    energy = (cs[:, starts + L] - cs[:, starts]).sum(axis=0)
+    rel = np.abs(S.astype(np.float64).sum(axis=1) / (N * energy) - 1)
+    say(f"  Parseval max rel {rel.max():.3e}")
+    assert rel.max() < 1e-5
     ctx.close()
