@@ -123,6 +123,43 @@ ispl_status ispl_find_plasma_line(ispl_ctx* ctx, const float* spectra,
                                   int32_t* peak_bin, float* peak_power,
                                   void* stream);
 
+/*
+ * Zoom DFT on the matrix cores: K bins of the N-point spectrum of every gate,
+ * starting at a per-gate bin, without the full transform.  Each gate's
+ * decoded rows are shifted so that its window starts at bin 0 and multiplied
+ * by one K x L DFT matrix shared by all gates and pulses, on BF16 or FP16
+ * MFMA with both operands split into high and low halves (three products,
+ * FP32 accumulation); decode, shift and the pulse sum stay FP32.  The result
+ * is the same quantity as ispl_integrate_spectra at those bins (Section 2.2,
+ * Eqs. 7-8), at the precision of the chosen split.
+ */
+typedef enum {
+  ISPL_ZOOM_BF16X3 = 0,  /* BF16 hi/lo split: ~16 significant bits per product */
+  ISPL_ZOOM_FP16X3 = 1   /* FP16 hi/lo split with per-pulse power-of-two scaling: ~22 bits */
+} ispl_zoom_precision;
+
+typedef struct ispl_zoom ispl_zoom; /* opaque; must not outlive its context */
+
+/* Builds the split DFT-matrix table for windows of n_bins bins (a multiple of
+ * 128, at most fft_len) of ctx's geometry.  Table size is 8 * n_bins *
+ * round_up(code_len, 64) bytes; ISPL_ERR_UNSUPPORTED above 512 MiB. */
+ispl_status ispl_zoom_create(ispl_ctx* ctx, int32_t n_bins, int32_t precision,
+                             ispl_zoom** out);
+
+/*
+ * spectra[g][j] (+)= sum_p | sum_{n<L} conj(c_p[n]) x_p[g0+g*s+n]
+ *                             * exp(-2 pi i (bin_start[g] + j) n / N) |^2,  j < n_bins.
+ *   samples, tx_code, tx_per_pulse, n_pulses, accumulate: as ispl_integrate_spectra.
+ *   bin_start  device int32 [n_gates]; any integer, taken modulo N.
+ *   spectra    device float [n_gates][n_bins].
+ */
+ispl_status ispl_zoom_spectra(ispl_zoom* zoom, const void* samples, const float* tx_code,
+                              int32_t tx_per_pulse, int32_t n_pulses,
+                              const int32_t* bin_start, float* spectra, int32_t accumulate,
+                              void* stream);
+
+void ispl_zoom_destroy(ispl_zoom* zoom);
+
 /* Frees the context and its device memory (synchronises its device first).
  * NULL is a no-op. */
 void ispl_destroy(ispl_ctx* ctx);

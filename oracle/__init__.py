@@ -12,4 +12,5 @@ from .ispl_oracle import (  # noqa: F401
     gate_windows,
     integrate_spectra,
     pulse_power_spectra,
+    window_spectra,
 )

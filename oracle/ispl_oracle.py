@@ -38,6 +38,7 @@ __all__ = [
     "integrate_spectra",
     "find_plasma_line",
     "bin_to_hz",
+    "window_spectra",
 ]
 
 
@@ -144,3 +145,15 @@ def bin_to_hz(k, fft_len: int, fs_hz: float):
     k = np.asarray(k, dtype=np.int64)
     signed = np.where(k < fft_len // 2, k, k - fft_len)
     return signed * (fs_hz / fft_len)
+
+
+def window_spectra(samples: np.ndarray, tx: np.ndarray, *, n_gates: int, gate_step: int,
+                   first_gate: int, fft_len: int, tx_per_pulse: bool, bin_start,
+                   n_bins: int) -> np.ndarray:
+    """S[g, (bin_start[g] + j) mod N] for j < n_bins: the integrated spectrum of
+    Eq. 8 restricted to one window of bins per gate.  float64 [G][n_bins]."""
+    full = integrate_spectra(samples, tx, n_gates=n_gates, gate_step=gate_step,
+                             first_gate=first_gate, fft_len=fft_len, tx_per_pulse=tx_per_pulse)
+    starts = np.asarray(bin_start, dtype=np.int64)
+    idx = np.mod(starts[:, None] + np.arange(n_bins)[None, :], fft_len)
+    return np.take_along_axis(full, idx, axis=1)

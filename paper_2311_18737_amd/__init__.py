@@ -16,6 +16,8 @@ from ._lib import (  # noqa: F401
     ISPL_ERR_OUT_OF_MEMORY,
     ISPL_ERR_UNSUPPORTED,
     ISPL_OK,
+    ISPL_ZOOM_BF16X3,
+    ISPL_ZOOM_FP16X3,
     IsplConfig,
     IsplError,
     LIB_PATH,
@@ -25,7 +27,7 @@ from ._lib import (  # noqa: F401
 
 def __getattr__(name):
     # torch-dependent pieces load lazily so the ABI can be inspected without torch
-    if name in ("Context", "make_config", "plan"):
+    if name in ("Context", "Zoom", "make_config", "plan"):
         from . import context
 
         return getattr(context, name)

@@ -19,11 +19,17 @@ ISPL_ERR_DEVICE = 4
 ISPL_SAMPLES_C64 = 0
 ISPL_SAMPLES_CI16 = 1
 
+ISPL_ZOOM_BF16X3 = 0
+ISPL_ZOOM_FP16X3 = 1
+
 EXPORTED = (
     "ispl_create",
     "ispl_integrate_spectra",
     "ispl_find_plasma_line",
     "ispl_destroy",
+    "ispl_zoom_create",
+    "ispl_zoom_spectra",
+    "ispl_zoom_destroy",
     "ispl_plan",
     "ispl_status_string",
     "ispl_last_error",
@@ -88,6 +94,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ispl_find_plasma_line.restype = i32
     lib.ispl_destroy.argtypes = [vp]
     lib.ispl_destroy.restype = None
+    lib.ispl_zoom_create.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
+    lib.ispl_zoom_create.restype = i32
+    lib.ispl_zoom_spectra.argtypes = [vp, vp, vp, i32, i32, vp, vp, i32, vp]
+    lib.ispl_zoom_spectra.restype = i32
+    lib.ispl_zoom_destroy.argtypes = [vp]
+    lib.ispl_zoom_destroy.restype = None
     lib.ispl_plan.argtypes = [ctypes.POINTER(IsplConfig), i32, ctypes.POINTER(i32),
                               ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.ispl_plan.restype = i32

@@ -167,3 +167,73 @@ class Context:
             ctypes.c_void_p(_stream_handle(stream, self.device)))
         check(st, "ispl_find_plasma_line")
         return out_bins, (out_power if want_power else None)
+
+
+_ZOOM_PRECISIONS = {"bf16x3": _lib.ISPL_ZOOM_BF16X3, "fp16x3": _lib.ISPL_ZOOM_FP16X3}
+
+
+class Zoom:
+    """K-bin windows of every gate's spectrum on the matrix cores
+    (ispl_zoom_create / ispl_zoom_spectra / ispl_zoom_destroy).  Keep the
+    parent Context open while this object is in use."""
+
+    def __init__(self, ctx: Context, n_bins: int, precision: str = "fp16x3"):
+        if precision not in _ZOOM_PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(_ZOOM_PRECISIONS)}")
+        self._lib = ctx._lib
+        self.ctx = ctx
+        self.n_bins = n_bins
+        self.precision = precision
+        h = ctypes.c_void_p()
+        check(self._lib.ispl_zoom_create(ctx._handle(), n_bins, _ZOOM_PRECISIONS[precision],
+                                         ctypes.byref(h)), "ispl_zoom_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ispl_zoom_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def spectra(self, samples: torch.Tensor, tx: torch.Tensor, bin_start: torch.Tensor, *,
+                out: Optional[torch.Tensor] = None, accumulate: bool = False,
+                stream=None) -> torch.Tensor:
+        """out[g][j] = sum_p |DFT of the decoded gate window at bin bin_start[g] + j|^2."""
+        if self._h is None:
+            raise RuntimeError("zoom is closed")
+        ctx = self.ctx
+        n_pulses = ctx._check_samples(samples)
+        _require(tx.device == ctx.device and tx.is_contiguous() and tx.dtype == torch.complex64,
+                 "tx must be contiguous complex64 on the device")
+        if tx.dim() == 1:
+            tx = tx.unsqueeze(0)
+        _require(tx.dim() == 2 and tx.shape[1] == ctx.code_len, "tx must be [P or 1][code_len]")
+        per_pulse = tx.shape[0] != 1
+        _require(not per_pulse or tx.shape[0] == n_pulses, "tx rows must be 1 or n_pulses")
+        _require(bin_start.device == ctx.device and bin_start.dtype == torch.int32
+                 and bin_start.is_contiguous() and tuple(bin_start.shape) == (ctx.n_gates,),
+                 "bin_start must be contiguous int32 [n_gates] on the device")
+        if out is None:
+            _require(not accumulate, "accumulate=True needs `out`")
+            out = torch.empty((ctx.n_gates, self.n_bins), dtype=torch.float32, device=ctx.device)
+        _require(out.device == ctx.device and out.dtype == torch.float32 and out.is_contiguous()
+                 and tuple(out.shape) == (ctx.n_gates, self.n_bins),
+                 "out must be contiguous float32 [n_gates][n_bins] on the device")
+        st = self._lib.ispl_zoom_spectra(
+            self._h, ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(tx.data_ptr()),
+            int(per_pulse), n_pulses, ctypes.c_void_p(bin_start.data_ptr()),
+            ctypes.c_void_p(out.data_ptr()), int(bool(accumulate)),
+            ctypes.c_void_p(_stream_handle(stream, ctx.device)))
+        check(st, "ispl_zoom_spectra")
+        return out

@@ -191,7 +191,68 @@ std::vector<float> twiddle_table(int n) {
 
 bool misaligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) != 0; }
 
+// Round to a 16-bit float: BF16 (round to nearest even on the FP32 bits) or
+// FP16 (the compiler's conversion).  Returns the bits and the value.
+uint16_t round16(double v, int precision, double* value) {
+  const float f = static_cast<float>(v);
+  if (precision == ISPL_ZOOM_BF16X3) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    const uint16_t h = static_cast<uint16_t>(u >> 16);
+    const uint32_t back = static_cast<uint32_t>(h) << 16;
+    float bf;
+    std::memcpy(&bf, &back, 4);
+    *value = bf;
+    return h;
+  }
+  const _Float16 h = static_cast<_Float16>(f);
+  uint16_t bits;
+  std::memcpy(&bits, &h, 2);
+  *value = static_cast<double>(static_cast<float>(h));
+  return bits;
+}
+
+// The real DFT-matrix of the zoom GEMM, split into high and low 16-bit parts,
+// in MFMA A-operand order: for row tile rt (32 rows), k-step ks (16 reduction
+// rows) and lane l, 8 values A[32 rt + l % 32][16 ks + 8 (l / 32) + i].
+// Rows 2j / 2j+1 give Re / Im of bin j, reduction rows 2n / 2n+1 take Re / Im
+// of sample n: A = [[cos, sin], [-sin, cos]] of theta = 2 pi ((j n) mod N) / N.
+void zoom_table(int n_fft, int n_bins, int code_len, int code_pad, int precision,
+                std::vector<uint16_t>& hi, std::vector<uint16_t>& lo) {
+  const int n_rt = 2 * n_bins / 32, n_ks = 2 * code_pad / 16;
+  hi.assign(static_cast<size_t>(n_rt) * n_ks * 64 * 8, 0);
+  lo.assign(hi.size(), 0);
+  size_t idx = 0;
+  for (int rt = 0; rt < n_rt; ++rt)
+    for (int ks = 0; ks < n_ks; ++ks)
+      for (int l = 0; l < 64; ++l)
+        for (int i = 0; i < 8; ++i, ++idx) {
+          const int row = 32 * rt + l % 32, k = 16 * ks + 8 * (l / 32) + i;
+          const int j = row / 2, n = k / 2;
+          double v = 0.0;
+          if (n < code_len) {
+            const int64_t m = (static_cast<int64_t>(j) * n) % n_fft;
+            const double th = 2.0 * M_PI * static_cast<double>(m) / n_fft;
+            const double c = std::cos(th), sn = std::sin(th);
+            v = (row % 2 == 0) ? (k % 2 == 0 ? c : sn) : (k % 2 == 0 ? -sn : c);
+          }
+          double hv, lv;
+          hi[idx] = round16(v, precision, &hv);
+          lo[idx] = round16(v - hv, precision, &lv);
+        }
+}
+
 }  // namespace
+
+struct ispl_zoom {
+  ispl_ctx* ctx;
+  int32_t n_bins;
+  int32_t precision;
+  int32_t code_pad;
+  void* a_hi;
+  void* a_lo;
+};
 
 extern "C" {
 
@@ -352,6 +413,117 @@ ispl_status ispl_integrate_spectra(ispl_ctx* ctx, const void* samples, const flo
     e = ispl::launch_reduce_chunks(ctx->partial, spectra, elems, pl.chunks, accumulate, s);
     if (e != hipSuccess) return hip_fail(e, "chunk reduce launch");
   }
+  return ok();
+}
+
+ispl_status ispl_zoom_create(ispl_ctx* ctx, int32_t n_bins, int32_t precision,
+                             ispl_zoom** out) {
+  if (!out) return fail(ISPL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ctx) return fail(ISPL_ERR_INVALID_ARG, "context is NULL");
+  const ispl_config& c = ctx->cfg;
+  if (precision != ISPL_ZOOM_BF16X3 && precision != ISPL_ZOOM_FP16X3)
+    return fail(ISPL_ERR_INVALID_ARG, "unknown zoom precision %d", precision);
+  if (n_bins < 128 || n_bins % 128 != 0 || n_bins > c.fft_len)
+    return fail(ISPL_ERR_INVALID_ARG, "n_bins %d: need a multiple of 128 in [128, fft_len %d]",
+                n_bins, c.fft_len);
+  const int32_t code_pad = (c.code_len + 63) / 64 * 64;
+  const int64_t bytes = int64_t{8} * n_bins * code_pad;
+  if (bytes > (int64_t{512} << 20))
+    return fail(ISPL_ERR_UNSUPPORTED, "zoom table of %lld bytes exceeds 512 MiB",
+                static_cast<long long>(bytes));
+  std::vector<uint16_t> hi, lo;
+  zoom_table(c.fft_len, n_bins, c.code_len, code_pad, precision, hi, lo);
+  DeviceGuard guard(c.device);
+  ispl_zoom* z = new (std::nothrow) ispl_zoom{};
+  if (!z) return fail(ISPL_ERR_OUT_OF_MEMORY, "host allocation");
+  z->ctx = ctx;
+  z->n_bins = n_bins;
+  z->precision = precision;
+  z->code_pad = code_pad;
+  const size_t half = hi.size() * sizeof(uint16_t);
+  hipError_t e = hipMalloc(&z->a_hi, half);
+  if (e == hipSuccess) e = hipMalloc(&z->a_lo, half);
+  if (e != hipSuccess) {
+    if (z->a_hi) (void)hipFree(z->a_hi);
+    delete z;
+    return fail(ISPL_ERR_OUT_OF_MEMORY, "zoom table: %s", hipGetErrorString(e));
+  }
+  e = hipMemcpy(z->a_hi, hi.data(), half, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(z->a_lo, lo.data(), half, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(z->a_hi);
+    (void)hipFree(z->a_lo);
+    delete z;
+    return hip_fail(e, "zoom table upload");
+  }
+  *out = z;
+  return ok();
+}
+
+void ispl_zoom_destroy(ispl_zoom* z) {
+  if (!z) return;
+  {
+    DeviceGuard guard(z->ctx->cfg.device);
+    (void)hipDeviceSynchronize();
+    if (z->a_hi) (void)hipFree(z->a_hi);
+    if (z->a_lo) (void)hipFree(z->a_lo);
+  }
+  delete z;
+}
+
+ispl_status ispl_zoom_spectra(ispl_zoom* z, const void* samples, const float* tx_code,
+                              int32_t tx_per_pulse, int32_t n_pulses, const int32_t* bin_start,
+                              float* spectra, int32_t accumulate, void* stream) {
+  if (!z) return fail(ISPL_ERR_INVALID_ARG, "zoom is NULL");
+  const ispl_config& c = z->ctx->cfg;
+  if (n_pulses < 0 || n_pulses > c.max_pulses)
+    return fail(ISPL_ERR_INVALID_ARG, "n_pulses %d outside [0, max_pulses %d]", n_pulses,
+                c.max_pulses);
+  if (!spectra || !bin_start) return fail(ISPL_ERR_INVALID_ARG, "spectra or bin_start is NULL");
+  if (misaligned(spectra, 4) || misaligned(bin_start, 4))
+    return fail(ISPL_ERR_INVALID_ARG, "spectra or bin_start not 4-byte aligned");
+  if (n_pulses > 0) {
+    if (!samples || !tx_code) return fail(ISPL_ERR_INVALID_ARG, "samples or tx_code is NULL");
+    const size_t sa = c.sample_type == ISPL_SAMPLES_CI16 ? 4 : 8;
+    if (misaligned(samples, sa) || misaligned(tx_code, 8))
+      return fail(ISPL_ERR_INVALID_ARG, "samples or tx_code misaligned");
+  }
+  if ((tx_per_pulse != 0 && tx_per_pulse != 1) || (accumulate != 0 && accumulate != 1))
+    return fail(ISPL_ERR_INVALID_ARG, "tx_per_pulse and accumulate must be 0 or 1");
+  DeviceGuard guard(c.device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n_pulses == 0) {
+    if (!accumulate) {
+      const hipError_t e =
+          ispl::launch_fill_zero(spectra, static_cast<int64_t>(c.n_gates) * z->n_bins, s);
+      if (e != hipSuccess) return hip_fail(e, "fill_zero launch");
+    }
+    return ok();
+  }
+  ispl::ZoomArgs a{};
+  a.samples = samples;
+  a.tx = tx_code;
+  a.twiddle = z->ctx->twiddle;
+  a.a_hi = z->a_hi;
+  a.a_lo = z->a_lo;
+  a.bin_start = bin_start;
+  a.out = spectra;
+  a.stride = c.pulse_stride;
+  a.n_fft = c.fft_len;
+  a.code_len = c.code_len;
+  a.code_pad = z->code_pad;
+  a.n_gates = c.n_gates;
+  a.gate_step = c.gate_step;
+  a.first_gate = c.first_gate;
+  a.n_pulses = n_pulses;
+  a.n_bins = z->n_bins;
+  a.tx_per_pulse = tx_per_pulse;
+  a.accumulate = accumulate;
+  a.sample_type = c.sample_type;
+  a.precision = z->precision;
+  const hipError_t e = ispl::launch_zoom(a, s);
+  if (e != hipSuccess) return hip_fail(e, "zoom launch");
   return ok();
 }
 

@@ -47,6 +47,32 @@ hipError_t launch_reduce_chunks(const float* partial, float* spectra, int64_t el
 
 hipError_t launch_fill_zero(float* dst, int64_t elems, hipStream_t stream);
 
+// Zoom DFT of a K-bin window per gate on the matrix cores.
+struct ZoomArgs {
+  const void* samples;      // [P][stride] ci16 or c64
+  const float* tx;          // complex64 pairs, [P][L] or [L]
+  const float* twiddle;     // complex64 pairs, W_N^i for i < N
+  const void* a_hi;         // DFT-matrix table, high halves, MFMA A-operand order
+  const void* a_lo;         // low halves
+  const int32_t* bin_start; // [G] first bin of each gate's window (taken mod N)
+  float* out;               // [G][K]
+  int64_t stride;
+  int32_t n_fft;            // N
+  int32_t code_len;         // L
+  int32_t code_pad;         // L rounded up to 64
+  int32_t n_gates;
+  int32_t gate_step;
+  int32_t first_gate;
+  int32_t n_pulses;
+  int32_t n_bins;           // K, a multiple of 128
+  int32_t tx_per_pulse;
+  int32_t accumulate;
+  int32_t sample_type;
+  int32_t precision;        // 0: BF16 x3, 1: FP16 x3
+};
+
+hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream);
+
 hipError_t launch_peak(const float* spectra, int32_t n_gates, int32_t n_fft, int32_t bin_lo,
                        int32_t bin_hi, int32_t* peak_bin, float* peak_power,
                        hipStream_t stream);

@@ -115,6 +115,11 @@ def test_plans_of_named_workloads(ispl_lib):
 
 def test_null_context_and_null_pointers(ispl_lib):
     vp = ctypes.c_void_p
+    z = ctypes.c_void_p(99)
+    assert ispl_lib.ispl_zoom_create(None, 256, 0, ctypes.byref(z)) == 1 and z.value is None
+    assert ispl_lib.ispl_zoom_create(None, 256, 0, None) == 1
+    assert ispl_lib.ispl_zoom_spectra(None, vp(16), vp(16), 1, 1, vp(16), vp(16), 0, None) == 1
+    ispl_lib.ispl_zoom_destroy(None)
     assert ispl_lib.ispl_integrate_spectra(None, vp(16), vp(16), 1, 1, vp(16), 0, None) == 1
     assert ispl_lib.ispl_find_plasma_line(None, vp(16), 0, 16, vp(16), None, None) == 1
     ispl_lib.ispl_destroy(None)
