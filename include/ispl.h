@@ -160,6 +160,50 @@ ispl_status ispl_zoom_spectra(ispl_zoom* zoom, const void* samples, const float*
 
 void ispl_zoom_destroy(ispl_zoom* zoom);
 
+/*
+ * Window-proposal network of the learned zoom.  It reads one integrated
+ * coarse spectrum per gate (ISPL_NET_LEN = 1024 bins) as the feature
+ * x[t] = log(max(S[t] / mean S, 1e-30)) and returns one logit per coarse bin:
+ * four circular 7-tap 1-D convolutions, 1 -> 32 -> 32 -> 32 -> 1 channels,
+ * ReLU after the first three.  Training minimises the softmax cross entropy
+ * against a two-hot target at the line's coarse position u (1 - frac(u) on
+ * floor(u), frac(u) on floor(u) + 1, modulo 1024) with Adam (beta 0.9,
+ * 0.999, eps 1e-8) on FP32 master weights; training kernels run in FP32.
+ * Parameters (ISPL_NET_PARAMS floats): W1[32][1][7] b1[32] W2[32][32][7]
+ * b2[32] W3[32][32][7] b3[32] W4[1][32][7] b4[1].  Not thread-safe; runs
+ * on the device it was created on.
+ */
+#define ISPL_NET_LEN 1024
+#define ISPL_NET_PARAMS 14881
+
+typedef struct ispl_net ispl_net;
+
+typedef enum {
+  ISPL_NET_FP32 = 0,  /* vector-ALU forward, FP32 weights and activations */
+  ISPL_NET_BF16 = 1   /* matrix-core forward, BF16 weights and activations, FP32 accumulation */
+} ispl_net_precision;
+
+/* Allocates parameters (zero), Adam state and the workspace of batches of up
+ * to max_batch gates on `device`. */
+ispl_status ispl_net_create(int32_t device, int32_t max_batch, ispl_net** out);
+void ispl_net_destroy(ispl_net* net);
+/* Host float arrays of ISPL_NET_PARAMS values; set_params also resets Adam. */
+ispl_status ispl_net_set_params(ispl_net* net, const float* host_params);
+ispl_status ispl_net_get_params(ispl_net* net, float* host_params);
+/* features[r][t] from spectra[r][t], device [rows][ISPL_NET_LEN] each. */
+ispl_status ispl_net_features(ispl_net* net, const float* spectra, int32_t rows,
+                              float* features, void* stream);
+/* logits[b][t] of features[b][t], device [batch][ISPL_NET_LEN], batch <= max_batch. */
+ispl_status ispl_net_forward(ispl_net* net, const float* features, int32_t batch,
+                             float* logits, int32_t precision, void* stream);
+/* Mean loss (device float [1]) and its gradient (device float [ISPL_NET_PARAMS])
+ * over a batch; target_pos device float [batch] in coarse-bin units. */
+ispl_status ispl_net_loss_grad(ispl_net* net, const float* features, const float* target_pos,
+                               int32_t batch, float* grad, float* loss, void* stream);
+/* loss_grad, then one Adam step of learning rate lr. */
+ispl_status ispl_net_train_step(ispl_net* net, const float* features, const float* target_pos,
+                                int32_t batch, float lr, float* loss, void* stream);
+
 /* Frees the context and its device memory (synchronises its device first).
  * NULL is a no-op. */
 void ispl_destroy(ispl_ctx* ctx);

@@ -22,6 +22,11 @@ ISPL_SAMPLES_CI16 = 1
 ISPL_ZOOM_BF16X3 = 0
 ISPL_ZOOM_FP16X3 = 1
 
+ISPL_NET_LEN = 1024
+ISPL_NET_PARAMS = 14881
+ISPL_NET_FP32 = 0
+ISPL_NET_BF16 = 1
+
 EXPORTED = (
     "ispl_create",
     "ispl_integrate_spectra",
@@ -30,6 +35,14 @@ EXPORTED = (
     "ispl_zoom_create",
     "ispl_zoom_spectra",
     "ispl_zoom_destroy",
+    "ispl_net_create",
+    "ispl_net_destroy",
+    "ispl_net_set_params",
+    "ispl_net_get_params",
+    "ispl_net_features",
+    "ispl_net_forward",
+    "ispl_net_loss_grad",
+    "ispl_net_train_step",
     "ispl_plan",
     "ispl_status_string",
     "ispl_last_error",
@@ -100,6 +113,22 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ispl_zoom_spectra.restype = i32
     lib.ispl_zoom_destroy.argtypes = [vp]
     lib.ispl_zoom_destroy.restype = None
+    lib.ispl_net_create.argtypes = [i32, i32, ctypes.POINTER(vp)]
+    lib.ispl_net_create.restype = i32
+    lib.ispl_net_destroy.argtypes = [vp]
+    lib.ispl_net_destroy.restype = None
+    lib.ispl_net_set_params.argtypes = [vp, vp]
+    lib.ispl_net_set_params.restype = i32
+    lib.ispl_net_get_params.argtypes = [vp, vp]
+    lib.ispl_net_get_params.restype = i32
+    lib.ispl_net_features.argtypes = [vp, vp, i32, vp, vp]
+    lib.ispl_net_features.restype = i32
+    lib.ispl_net_forward.argtypes = [vp, vp, i32, vp, i32, vp]
+    lib.ispl_net_forward.restype = i32
+    lib.ispl_net_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    lib.ispl_net_loss_grad.restype = i32
+    lib.ispl_net_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp]
+    lib.ispl_net_train_step.restype = i32
     lib.ispl_plan.argtypes = [ctypes.POINTER(IsplConfig), i32, ctypes.POINTER(i32),
                               ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.ispl_plan.restype = i32

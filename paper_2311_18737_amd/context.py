@@ -237,3 +237,103 @@ class Zoom:
             ctypes.c_void_p(_stream_handle(stream, ctx.device)))
         check(st, "ispl_zoom_spectra")
         return out
+
+
+_NET_PRECISIONS = {"fp32": _lib.ISPL_NET_FP32, "bf16": _lib.ISPL_NET_BF16}
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Net:
+    """Window-proposal network of the learned zoom (ispl_net_*): 1024 coarse
+    bins in, one logit per bin out; FP32 training kernels, FP32 or BF16
+    matrix-core forward."""
+
+    LEN = _lib.ISPL_NET_LEN
+    N_PARAMS = _lib.ISPL_NET_PARAMS
+
+    def __init__(self, max_batch: int, device: int = 0):
+        self._lib = load_library()
+        self.device = torch.device("cuda", device)
+        self.max_batch = max_batch
+        h = ctypes.c_void_p()
+        check(self._lib.ispl_net_create(device, max_batch, ctypes.byref(h)), "ispl_net_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ispl_net_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params) -> None:
+        import numpy as np
+
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        _require(p.shape == (self.N_PARAMS,), f"params must have {self.N_PARAMS} values")
+        check(self._lib.ispl_net_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p)),
+              "ispl_net_set_params")
+
+    def get_params(self):
+        import numpy as np
+
+        p = np.empty(self.N_PARAMS, dtype=np.float32)
+        check(self._lib.ispl_net_get_params(self._h, p.ctypes.data_as(ctypes.c_void_p)),
+              "ispl_net_get_params")
+        return p
+
+    def _rows(self, t: torch.Tensor, what: str) -> int:
+        _require(t.device == self.device and t.dtype == torch.float32 and t.is_contiguous()
+                 and t.dim() == 2 and t.shape[1] == self.LEN,
+                 f"{what} must be contiguous float32 [rows][{self.LEN}] on the device")
+        return t.shape[0]
+
+    def features(self, spectra: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None):
+        rows = self._rows(spectra, "spectra")
+        out = torch.empty_like(spectra) if out is None else out
+        self._rows(out, "out")
+        check(self._lib.ispl_net_features(self._h, _ptr(spectra), rows, _ptr(out),
+                                          ctypes.c_void_p(_stream_handle(stream, self.device))),
+              "ispl_net_features")
+        return out
+
+    def forward(self, features: torch.Tensor, precision: str = "fp32",
+                out: Optional[torch.Tensor] = None, stream=None):
+        rows = self._rows(features, "features")
+        out = torch.empty_like(features) if out is None else out
+        self._rows(out, "out")
+        check(self._lib.ispl_net_forward(self._h, _ptr(features), rows, _ptr(out),
+                                         _NET_PRECISIONS[precision],
+                                         ctypes.c_void_p(_stream_handle(stream, self.device))),
+              "ispl_net_forward")
+        return out
+
+    def loss_grad(self, features: torch.Tensor, target_pos: torch.Tensor, stream=None):
+        rows = self._rows(features, "features")
+        _require(target_pos.dtype == torch.float32 and target_pos.shape == (rows,)
+                 and target_pos.is_contiguous() and target_pos.device == self.device,
+                 "target_pos must be float32 [rows] on the device")
+        grad = torch.empty(self.N_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        check(self._lib.ispl_net_loss_grad(self._h, _ptr(features), _ptr(target_pos), rows,
+                                           _ptr(grad), _ptr(loss),
+                                           ctypes.c_void_p(_stream_handle(stream, self.device))),
+              "ispl_net_loss_grad")
+        return loss, grad
+
+    def train_step(self, features: torch.Tensor, target_pos: torch.Tensor, lr: float,
+                   loss: Optional[torch.Tensor] = None, stream=None):
+        rows = self._rows(features, "features")
+        loss = torch.empty(1, dtype=torch.float32, device=self.device) if loss is None else loss
+        check(self._lib.ispl_net_train_step(self._h, _ptr(features), _ptr(target_pos), rows,
+                                            float(lr), _ptr(loss),
+                                            ctypes.c_void_p(_stream_handle(stream, self.device))),
+              "ispl_net_train_step")
+        return loss

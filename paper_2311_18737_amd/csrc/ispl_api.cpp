@@ -527,6 +527,181 @@ ispl_status ispl_zoom_spectra(ispl_zoom* z, const void* samples, const float* tx
   return ok();
 }
 
+}  // extern "C"
+
+struct ispl_net {
+  int32_t device;
+  int32_t max_batch;
+  int32_t step;
+  ispl::NetWork w;
+  float* grad;
+  float* adam_m;
+  float* adam_v;
+  float* bf16_weights;  // matrix-core copies, rebuilt when the parameters change
+  bool bf16_stale;
+};
+
+namespace {
+
+void net_free(ispl_net* n) {
+  void* bufs[] = {n->w.params, n->w.a1, n->w.a2, n->w.a3, n->w.logits, n->w.dz4, n->w.dzA,
+                  n->w.dzB, n->w.part, n->w.loss, n->grad, n->adam_m, n->adam_v,
+                  n->bf16_weights};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+ispl_status ispl_net_create(int32_t device, int32_t max_batch, ispl_net** out) {
+  if (!out) return fail(ISPL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (max_batch < 1 || max_batch > 65536)
+    return fail(ISPL_ERR_INVALID_ARG, "max_batch %d outside [1, 65536]", max_batch);
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0)
+    return fail(ISPL_ERR_DEVICE, "no HIP device (%s)", hipGetErrorString(e));
+  if (device < 0 || device >= count) return fail(ISPL_ERR_DEVICE, "device %d of %d", device, count);
+  DeviceGuard guard(device);
+  ispl_net* n = new (std::nothrow) ispl_net{};
+  if (!n) return fail(ISPL_ERR_OUT_OF_MEMORY, "host allocation");
+  n->device = device;
+  n->max_batch = max_batch;
+  const size_t B = static_cast<size_t>(max_batch), T = ispl::NET_LEN, P = ispl::NET_PARAMS;
+  struct { float** p; size_t n; } plan[] = {
+      {&n->w.params, P}, {&n->w.a1, B * 32 * T}, {&n->w.a2, B * 32 * T}, {&n->w.a3, B * 32 * T},
+      {&n->w.logits, B * T}, {&n->w.dz4, B * T}, {&n->w.dzA, B * 32 * T}, {&n->w.dzB, B * 32 * T},
+      {&n->w.part, B * P}, {&n->w.loss, B}, {&n->grad, P}, {&n->adam_m, P}, {&n->adam_v, P},
+      {&n->bf16_weights, (ispl::net_bf16_bytes() + sizeof(float) - 1) / sizeof(float)}};
+  for (auto& a : plan) {
+    e = hipMalloc(reinterpret_cast<void**>(a.p), a.n * sizeof(float));
+    if (e != hipSuccess) {
+      net_free(n);
+      delete n;
+      return fail(ISPL_ERR_OUT_OF_MEMORY, "network workspace: %s", hipGetErrorString(e));
+    }
+  }
+  for (float* z : {n->w.params, n->adam_m, n->adam_v}) (void)hipMemset(z, 0, P * sizeof(float));
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    net_free(n);
+    delete n;
+    return hip_fail(e, "network init");
+  }
+  n->bf16_stale = true;
+  *out = n;
+  return ok();
+}
+
+void ispl_net_destroy(ispl_net* n) {
+  if (!n) return;
+  {
+    DeviceGuard guard(n->device);
+    (void)hipDeviceSynchronize();
+    net_free(n);
+  }
+  delete n;
+}
+
+ispl_status ispl_net_set_params(ispl_net* n, const float* host_params) {
+  if (!n || !host_params) return fail(ISPL_ERR_INVALID_ARG, "net or params is NULL");
+  DeviceGuard guard(n->device);
+  const size_t bytes = ispl::NET_PARAMS * sizeof(float);
+  hipError_t e = hipMemcpy(n->w.params, host_params, bytes, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(n->adam_m, 0, bytes);
+  if (e == hipSuccess) e = hipMemset(n->adam_v, 0, bytes);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "set_params");
+  n->step = 0;
+  n->bf16_stale = true;
+  return ok();
+}
+
+ispl_status ispl_net_get_params(ispl_net* n, float* host_params) {
+  if (!n || !host_params) return fail(ISPL_ERR_INVALID_ARG, "net or params is NULL");
+  DeviceGuard guard(n->device);
+  const hipError_t e = hipMemcpy(host_params, n->w.params, ispl::NET_PARAMS * sizeof(float),
+                                 hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "get_params");
+  return ok();
+}
+
+ispl_status ispl_net_features(ispl_net* n, const float* spectra, int32_t rows, float* features,
+                              void* stream) {
+  if (!n) return fail(ISPL_ERR_INVALID_ARG, "NULL net");
+  if (rows < 0) return fail(ISPL_ERR_INVALID_ARG, "rows %d < 0", rows);
+  if (rows == 0) return ok();  // empty tensors may carry NULL pointers
+  if (!spectra || !features) return fail(ISPL_ERR_INVALID_ARG, "NULL argument");
+  if (misaligned(spectra, 16) || misaligned(features, 16))
+    return fail(ISPL_ERR_INVALID_ARG, "spectra and features must be 16-byte aligned");
+  DeviceGuard guard(n->device);
+  const hipError_t e = ispl::launch_net_features(spectra, rows, features,
+                                                 static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "features launch");
+  return ok();
+}
+
+ispl_status ispl_net_forward(ispl_net* n, const float* features, int32_t batch, float* logits,
+                             int32_t precision, void* stream) {
+  if (!n) return fail(ISPL_ERR_INVALID_ARG, "NULL net");
+  if (batch < 0 || batch > n->max_batch)
+    return fail(ISPL_ERR_INVALID_ARG, "batch %d outside [0, max_batch %d]", batch, n->max_batch);
+  if (precision != ISPL_NET_FP32 && precision != ISPL_NET_BF16)
+    return fail(ISPL_ERR_INVALID_ARG, "unknown precision %d", precision);
+  if (batch == 0) return ok();  // empty tensors may carry NULL pointers
+  if (!features || !logits) return fail(ISPL_ERR_INVALID_ARG, "NULL argument");
+  if (misaligned(features, 16) || misaligned(logits, 16))
+    return fail(ISPL_ERR_INVALID_ARG, "features and logits must be 16-byte aligned");
+  DeviceGuard guard(n->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  if (precision == ISPL_NET_BF16) {
+    if (n->bf16_stale) {
+      e = ispl::launch_net_prep_bf16(n->w.params, n->bf16_weights, s);
+      if (e != hipSuccess) return hip_fail(e, "bf16 weight prep launch");
+      n->bf16_stale = false;
+    }
+    e = ispl::launch_net_forward_bf16(n->bf16_weights, features, batch, logits, s);
+  } else {
+    e = ispl::launch_net_forward_f32(n->w, features, batch, logits, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "forward launch");
+  return ok();
+}
+
+ispl_status ispl_net_loss_grad(ispl_net* n, const float* features, const float* target_pos,
+                               int32_t batch, float* grad, float* loss, void* stream) {
+  if (!n || !features || !target_pos || !grad || !loss)
+    return fail(ISPL_ERR_INVALID_ARG, "NULL argument");
+  if (batch < 1 || batch > n->max_batch)
+    return fail(ISPL_ERR_INVALID_ARG, "batch %d outside [1, max_batch %d]", batch, n->max_batch);
+  if (misaligned(features, 16)) return fail(ISPL_ERR_INVALID_ARG, "features not 16-byte aligned");
+  DeviceGuard guard(n->device);
+  const hipError_t e = ispl::launch_net_loss_grad(n->w, features, target_pos, batch, grad, loss,
+                                                  static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "loss_grad launch");
+  return ok();
+}
+
+ispl_status ispl_net_train_step(ispl_net* n, const float* features, const float* target_pos,
+                                int32_t batch, float lr, float* loss, void* stream) {
+  const ispl_status st = ispl_net_loss_grad(n, features, target_pos, batch, n ? n->grad : nullptr,
+                                            loss, stream);
+  if (st != ISPL_OK) return st;
+  if (!(lr > 0.f)) return fail(ISPL_ERR_INVALID_ARG, "learning rate must be > 0");
+  DeviceGuard guard(n->device);
+  n->step += 1;
+  n->bf16_stale = true;
+  const hipError_t e = ispl::launch_adam(n->w.params, n->grad, n->adam_m, n->adam_v,
+                                         ispl::NET_PARAMS, lr, n->step,
+                                         static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "adam launch");
+  return ok();
+}
+
 ispl_status ispl_find_plasma_line(ispl_ctx* ctx, const float* spectra, int32_t bin_lo,
                                   int32_t bin_hi, int32_t* peak_bin, float* peak_power,
                                   void* stream) {

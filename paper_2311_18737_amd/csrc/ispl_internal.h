@@ -73,6 +73,35 @@ struct ZoomArgs {
 
 hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream);
 
+// Window-proposal network (learned zoom).
+constexpr int NET_LEN = 1024;      // coarse bins per gate
+constexpr int NET_PARAMS = 14881;  // 4 circular 7-tap conv layers, 1-32-32-32-1 channels
+
+struct NetWork {  // device buffers of a training batch (FP32)
+  float* params;  // [NET_PARAMS]
+  float* a1;      // [B][32][T] activations after layers 1..3
+  float* a2;
+  float* a3;
+  float* logits;  // [B][T]
+  float* dz4;     // [B][T]
+  float* dzA;     // [B][32][T] gradient ping-pong
+  float* dzB;
+  float* part;    // [B][NET_PARAMS] per-gate weight gradients
+  float* loss;    // [B]
+};
+
+hipError_t launch_net_features(const float* spectra, int rows, float* out, hipStream_t s);
+hipError_t launch_net_forward_f32(const NetWork& w, const float* x, int batch, float* logits,
+                                  hipStream_t s);
+hipError_t launch_net_loss_grad(const NetWork& w, const float* x, const float* target_pos,
+                                int batch, float* grad, float* loss_mean, hipStream_t s);
+size_t net_bf16_bytes();  // matrix-core weight table of the BF16 forward
+hipError_t launch_net_prep_bf16(const float* params, void* table, hipStream_t s);
+hipError_t launch_net_forward_bf16(const void* table, const float* x, int batch, float* logits,
+                                   hipStream_t s);
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int n, float lr,
+                       int step, hipStream_t s);
+
 hipError_t launch_peak(const float* spectra, int32_t n_gates, int32_t n_fft, int32_t bin_lo,
                        int32_t bin_hi, int32_t* peak_bin, float* peak_power,
                        hipStream_t stream);
