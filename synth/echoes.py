@@ -16,12 +16,15 @@ plasma line, so for pulse p and range r with start sample t_r = g0 + r*s:
     f_{p,r}  = f_line(r) + delta_{p,r},  delta ~ N(0, (w / 2.3548)**2)
 
 (with ``echo_stride`` q > 1 only every q-th range cell echoes, which keeps
-drawing workloads with long codes and thousands of gates cheap).
+drawing workloads with long codes and thousands of gates cheap).  With
+``snr_db_range`` set, rho is drawn per range cell, uniformly in dB.
 
 f_line(r) follows an alpha-Chapman electron-density layer: the plasma
 frequency scales with the square root of density, so
 f_line = f_peak * exp((1 - z - exp(-z)) / 4) with z = (h - 300 km) / 50 km,
-and the gate altitudes h run linearly over [200, 600] km.  The plasma line
+and the gate altitudes h run linearly over [200, 600] km.  The "uniform" line
+model instead draws every range cell's line frequency independently, uniform
+over ``f_peak_hz`` (the learned-zoom workload, lines anywhere in 1-15 MHz).  The plasma line
 sits at roughly the plasma frequency (Section 2.1, Eq. 1, first term); the
 temperature and gyro terms of Eq. 1 are not modelled.
 
@@ -46,6 +49,7 @@ _STREAM_AMPS = 1
 _STREAM_FPEAK = 2
 _STREAM_JITTER = 3
 _STREAM_NOISE = 4
+_STREAM_SNR = 5
 
 
 @dataclass(frozen=True)
@@ -64,6 +68,10 @@ class EchoConfig:
     fs_hz: float = FS_HZ
     f_peak_hz: tuple = (6e6, 6e6)  # uniform draw over [lo, hi]; lo == hi fixes it
     snr_db: float = -10.0
+    # "chapman": one peak frequency per dataset, each gate's line on the layer
+    # profile; "uniform": every gate draws its own line frequency from f_peak_hz
+    line_model: str = "chapman"
+    snr_db_range: Optional[tuple] = None  # per-gate uniform SNR draw (replaces snr_db)
     line_width_hz: float = 0.0
     alt_km: tuple = (200.0, 600.0)
     int16_scale: float = 256.0  # counts per unit amplitude for "ci16"
@@ -108,6 +116,12 @@ CONFIGS = {
         name="paper", cfg_id=6, n_pulses=100, n_gates=4096, code_len=16384,
         fft_len=16384, sample_type="c64", f_peak_hz=(6e6, 6e6), snr_db=-10.0,
         echo_stride=64),
+    # learned-zoom workload: the small shape with N = 16384 (1024-bin coarse
+    # spectra feed the window-proposal network), independent lines per gate
+    "zoom": EchoConfig(
+        name="zoom", cfg_id=5, n_pulses=100, n_gates=64, code_len=256, fft_len=16384,
+        sample_type="c64", f_peak_hz=(1e6, 15e6), line_model="uniform",
+        snr_db_range=(-25.0, -5.0)),
 }
 
 
@@ -144,7 +158,8 @@ class Dataset:
     tx: np.ndarray  # complex64 [P or 1][L]
     f_line_hz: np.ndarray  # float64 [G], the line frequency of every gate
     f_peak_hz: float
-    rho: float
+    rho: float  # echo power per sample (the mean over gates when it varies)
+    rho_gate: Optional[np.ndarray] = None  # float64 [G] when SNR is drawn per gate
 
     @property
     def tx_per_pulse(self) -> bool:
@@ -197,15 +212,18 @@ def _cache_key(cfg: EchoConfig, seed: int) -> str:
 def _cached(cfg: EchoConfig, seed: int, progress, cache_dir: str) -> Dataset:
     os.makedirs(cache_dir, exist_ok=True)
     stem = os.path.join(cache_dir, f"{cfg.name}_{_cache_key(cfg, seed)}")
-    files = {k: f"{stem}_{k}.npy" for k in ("samples", "tx", "fline", "scalars")}
+    files = {k: f"{stem}_{k}.npy" for k in ("samples", "tx", "fline", "scalars", "rho")}
     if all(os.path.exists(f) for f in files.values()):
         sc = np.load(files["scalars"])
+        rg = np.load(files["rho"])
         return Dataset(cfg=cfg, seed=seed, samples=np.load(files["samples"]),
                        tx=np.load(files["tx"]), f_line_hz=np.load(files["fline"]),
-                       f_peak_hz=float(sc[0]), rho=float(sc[1]))
+                       f_peak_hz=float(sc[0]), rho=float(sc[1]),
+                       rho_gate=rg if cfg.snr_db_range is not None else None)
     d = _draw(cfg, seed, progress)
+    rg = d.rho_gate if d.rho_gate is not None else np.full(cfg.n_gates, d.rho)
     for k, arr in (("samples", d.samples), ("tx", d.tx), ("fline", d.f_line_hz),
-                   ("scalars", np.array([d.f_peak_hz, d.rho]))):
+                   ("scalars", np.array([d.f_peak_hz, d.rho])), ("rho", rg)):
         tmp = files[k] + f".{os.getpid()}.tmp.npy"
         np.save(tmp, arr)
         os.replace(tmp, files[k])
@@ -216,11 +234,25 @@ def _draw(cfg: EchoConfig, seed: int, progress) -> Dataset:
     P, G, L = cfg.n_pulses, cfg.n_gates, cfg.code_len
     s, g0 = cfg.gate_step, cfg.first_gate
     stride = cfg.pulse_stride
-    rho = 10.0 ** (cfg.snr_db / 10.0)
-
     lo, hi = cfg.f_peak_hz
-    f_peak = float(lo) if lo == hi else float(_rng(cfg, seed, _STREAM_FPEAK).uniform(lo, hi))
-    f_line = chapman_plasma_freq(gate_altitudes_km(G, cfg.alt_km), f_peak)
+    rng_f = _rng(cfg, seed, _STREAM_FPEAK)
+    if cfg.line_model == "chapman":
+        f_peak = float(lo) if lo == hi else float(rng_f.uniform(lo, hi))
+        f_line = chapman_plasma_freq(gate_altitudes_km(G, cfg.alt_km), f_peak)
+    elif cfg.line_model == "uniform":
+        f_line = rng_f.uniform(lo, hi, size=G)
+        f_peak = float(f_line.max())
+    else:
+        raise ValueError(f"unknown line_model {cfg.line_model!r}")
+    if cfg.snr_db_range is None:
+        rho_gate = None
+        rho = 10.0 ** (cfg.snr_db / 10.0)
+        amp = np.sqrt(rho / 2.0)
+    else:
+        snr = _rng(cfg, seed, _STREAM_SNR).uniform(cfg.snr_db_range[0], cfg.snr_db_range[1], size=G)
+        rho_gate = 10.0 ** (snr / 10.0)
+        rho = float(rho_gate.mean())
+        amp = np.sqrt(rho_gate / 2.0)
 
     tx = draw_codes(cfg, seed)
     rng_a = _rng(cfg, seed, _STREAM_AMPS)
@@ -240,7 +272,7 @@ def _draw(cfg: EchoConfig, seed: int, progress) -> Dataset:
     echo_r = np.arange(0, G, max(1, cfg.echo_stride))
     for p in range(P):
         c = tx[p if cfg.tx_per_pulse else 0]
-        a = (rng_a.standard_normal(G) + 1j * rng_a.standard_normal(G)) * np.sqrt(rho / 2.0)
+        a = (rng_a.standard_normal(G) + 1j * rng_a.standard_normal(G)) * amp
         f = f_line + (rng_j.standard_normal(G) * sig_w if sig_w > 0 else 0.0)
         a, f = a[echo_r], np.broadcast_to(f, (G,))[echo_r]
         # phase in cycles, reduced to [0, 1) in float64 before the float32 trig call
@@ -278,7 +310,7 @@ def _draw(cfg: EchoConfig, seed: int, progress) -> Dataset:
     else:
         raise ValueError(f"unknown sample_type {cfg.sample_type!r}")
     return Dataset(cfg=cfg, seed=seed, samples=samples, tx=tx, f_line_hz=f_line,
-                   f_peak_hz=f_peak, rho=rho)
+                   f_peak_hz=f_peak, rho=rho, rho_gate=rho_gate)
 
 
 def random_inputs(n_pulses: int, stride: int, code_len: int, *, sample_type: str = "c64",

@@ -109,3 +109,39 @@ def test_integrated_spectrum_matches_model_expectation():
         sd_pulse = np.sqrt(L + (d.rho ** 2) * np.sum(w.astype(float) ** 2))
         assert abs(floor_meas - floor_model) < 5.0 * sd_pulse / np.sqrt(P)
         assert int(np.argmax(S[g])) in {(truth[g] + j) % cfg.fft_len for j in (-1, 0, 1)}
+
+
+def test_zoom_workload_draws_lines_and_snr_per_gate():
+    cfg = CONFIGS["zoom"]
+    d = make_dataset(cfg, 11, cache_dir=None)
+    G = cfg.n_gates
+    assert d.f_line_hz.shape == (G,) and d.rho_gate.shape == (G,)
+    assert np.all((d.f_line_hz >= 1e6) & (d.f_line_hz <= 15e6))
+    snr = 10 * np.log10(d.rho_gate)
+    assert np.all((snr >= -25) & (snr <= -5))
+    assert np.std(d.f_line_hz) > 2e6 and np.std(snr) > 3  # independent draws, not one value
+    again = make_dataset(cfg, 11, cache_dir=None)
+    assert np.array_equal(again.samples, d.samples)
+    other = make_dataset(cfg, 12, cache_dir=None)
+    assert not np.array_equal(other.f_line_hz, d.f_line_hz)
+    # a line above fs/2 aliases: truth bin = round(f N / fs) mod N
+    tb = d.truth_bin()
+    assert np.all((tb >= 0) & (tb < cfg.fft_len))
+
+
+def test_zoom_workload_line_power_follows_the_gate_snr(tmp_path):
+    """Strong gates show their line: decoded with the code, the full-resolution
+    bin of a gate's line carries about rho L^2 per pulse over a floor of about
+    L (1 + sum of overlapping echo power)."""
+    from oracle import integrate_spectra
+    cfg = CONFIGS["zoom"].replace(n_pulses=20)
+    d = make_dataset(cfg, 2, cache_dir=str(tmp_path))
+    S = integrate_spectra(d.samples, d.tx, n_gates=cfg.n_gates, gate_step=cfg.gate_step,
+                          first_gate=0, fft_len=2048, tx_per_pulse=True)
+    tb = d.truth_bin(2048)
+    strong = np.nonzero(10 * np.log10(d.rho_gate) > -10)[0]
+    hits = [abs(((np.argmax(S[g]) - tb[g] + 1024) % 2048) - 1024) <= 2 for g in strong]
+    assert len(strong) >= 10 and np.mean(hits) >= 0.9
+    # the cache round-trips the per-gate SNR
+    d2 = make_dataset(cfg, 2, cache_dir=str(tmp_path))
+    assert np.array_equal(d2.rho_gate, d.rho_gate)
