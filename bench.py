@@ -232,6 +232,113 @@ def zoom_study(steps: int, seed: int, dev):
     return out
 
 
+def learned_zoom_study(steps: int, seed: int, dev, shapes=("c1", "large")):
+    """Learned zoom against the plain path on the same held-out data.
+
+    Plain: ispl_integrate_spectra at N = 16384 for every gate, then
+    ispl_find_plasma_line.  Learned: ispl_lzoom_peaks (coarse spectra at
+    N = 1024, BF16 network, window decision, 256-bin FP16x3 zoom where the
+    confidence is >= 0.9, full-resolution fallback elsewhere).  Reports both
+    times (HIP events on the launch stream, median of `steps`), the speedup,
+    the zoomed fraction and the fraction of gates whose learned peak lies
+    within one fine bin of the plain path's.
+    """
+    import numpy as np
+    import torch
+
+    import paper_2311_18737_amd as ispl
+    from paper_2311_18737_amd.zoom_training import EVAL_SEED0, load_weights
+    from synth import CONFIGS, make_dataset
+
+    stream = torch.cuda.current_stream(dev)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in ev]))
+
+    params = load_weights()
+    net = ispl.Net(1)
+    net.set_params(params)
+    base = CONFIGS["zoom"]
+    variants = {"c1": (base, "learned-zoom workload on the small shape: 100 pulses x 64 gates, "
+                             "code length 256, lines U(1,15) MHz, SNR U(-25,-5) dB per gate"),
+                "large": (base.replace(n_pulses=1000, n_gates=1000),
+                          "same content at 1000 pulses x 1000 gates")}
+    out = {}
+    for key in shapes:
+        cfg, text = variants[key]
+        d = make_dataset(cfg, EVAL_SEED0 + 500 + seed)
+        xs = torch.from_numpy(d.samples).to(dev)
+        xt = torch.from_numpy(d.tx).to(dev)
+        geo = dict(code_len=cfg.code_len, n_gates=cfg.n_gates, gate_step=cfg.gate_step,
+                   first_gate=cfg.first_gate, pulse_stride=cfg.pulse_stride,
+                   sample_type=cfg.sample_type, max_pulses=cfg.n_pulses)
+        ctx = ispl.Context(fft_len=cfg.fft_len, device=0, **geo)
+        lz = ispl.LearnedZoom(net, fft_len=cfg.fft_len, window_bins=256, threshold=0.9, **geo)
+        S = torch.empty((cfg.n_gates, cfg.fft_len), dtype=torch.float32, device=dev)
+        pb = torch.empty(cfg.n_gates, dtype=torch.int32, device=dev)
+        lb = torch.empty(cfg.n_gates, dtype=torch.int32, device=dev)
+        lp = torch.empty(cfg.n_gates, dtype=torch.float32, device=dev)
+
+        def plain(st=stream):
+            ctx.integrate_spectra(xs, xt, out=S, stream=st)
+            ctx.find_plasma_line(S, out_bins=pb, want_power=False, stream=st)
+
+        def learned(st=stream):
+            lz.peaks(xs, xt, out_bins=lb, out_power=lp, stream=st)
+
+        t_plain = timed(plain)
+        t_learned = timed(learned)
+        torch.cuda.synchronize()
+        n_zoom = int(lz.view()["counts"][0].item())
+        e = np.abs(lb.cpu().numpy().astype(np.int64) - pb.cpu().numpy().astype(np.int64))
+        e = np.minimum(e, cfg.fft_len - e)
+        out[key] = {"workload": text, "plain_ms": t_plain, "learned_ms": t_learned,
+                    "speedup": t_plain / t_learned,
+                    "zoomed_fraction": n_zoom / cfg.n_gates,
+                    "within_1_bin_of_plain": float(np.mean(e <= 1))}
+        # the same two paths replayed from HIP graphs (launch overhead removed);
+        # every replay is checked against the eager result
+        try:
+            ref_p, ref_l = pb.clone(), lb.clone()
+            graphs = {}
+            for name, fn in (("plain", plain), ("learned", learned)):
+                side = torch.cuda.Stream(dev)
+                side.wait_stream(stream)
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g, stream=side):
+                    fn(side)  # launches on the capturing stream
+                stream.wait_stream(side)
+                graphs[name] = g
+            times = {}
+            for name, g in graphs.items():
+                pb.fill_(-1)
+                lb.fill_(-1)
+                times[name] = timed(g.replay)
+                torch.cuda.synchronize()
+                same = torch.equal(pb, ref_p) if name == "plain" else torch.equal(lb, ref_l)
+                if not same:
+                    raise RuntimeError(f"{name} graph replay differs from the eager result")
+            out[key]["graph"] = {"plain_ms": times["plain"], "learned_ms": times["learned"],
+                                 "speedup": times["plain"] / times["learned"]}
+        except Exception as exc:  # reported, never hidden
+            out[key]["graph"] = {"error": repr(exc)}
+        log(f"learned zoom {key}: {out[key]}")
+        lz.close()
+        ctx.close()
+    net.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +351,8 @@ def main():
                     help="timed runs of the paper's Section 4 workload (0 = skip)")
     ap.add_argument("--zoom-steps", type=int, default=10,
                     help="timed runs of the matrix-core zoom DFT study (0 = skip)")
+    ap.add_argument("--lzoom-steps", type=int, default=20,
+                    help="timed runs of the learned-zoom study (0 = skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -327,6 +436,8 @@ def main():
 
     paper = paper_workload(args.paper_steps, args.seed, dev) if args.paper_steps > 0 else None
     zoom = zoom_study(args.zoom_steps, args.seed, dev) if args.zoom_steps > 0 else None
+    lzoom = (learned_zoom_study(args.lzoom_steps, args.seed, dev)
+             if args.lzoom_steps > 0 else None)
 
     cpu = None
     if args.cpu_budget > 0:
@@ -374,6 +485,7 @@ def main():
         "realtime_factor": (cfg.n_pulses * 10e-3) / (ms_per_step / 1e3),
         "paper_workload": paper,
         "zoom": zoom,
+        "learned_zoom": lzoom,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

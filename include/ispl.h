@@ -124,6 +124,26 @@ ispl_status ispl_find_plasma_line(ispl_ctx* ctx, const float* spectra,
                                   void* stream);
 
 /*
+ * Gate-list variants: the same computation restricted to the gates
+ * gate_list[i], i < *gate_count, where gate_list is a device int32 array of
+ * n_gates entries and gate_count a device int32 read by the kernels (so a
+ * list built on the device needs no host round trip).  Rows of other gates
+ * of spectra / peak_bin / peak_power are left untouched; entries outside
+ * [0, n_gates) are skipped; the listed gates must be distinct.  Both
+ * pointers are required (ISPL_ERR_INVALID_ARG when NULL).  Used for the
+ * full-resolution fallback of the learned zoom.
+ */
+ispl_status ispl_integrate_spectra_gates(ispl_ctx* ctx, const void* samples,
+                                         const float* tx_code, int32_t tx_per_pulse,
+                                         int32_t n_pulses, const int32_t* gate_list,
+                                         const int32_t* gate_count, float* spectra,
+                                         int32_t accumulate, void* stream);
+ispl_status ispl_find_plasma_line_gates(ispl_ctx* ctx, const float* spectra, int32_t bin_lo,
+                                        int32_t bin_hi, const int32_t* gate_list,
+                                        const int32_t* gate_count, int32_t* peak_bin,
+                                        float* peak_power, void* stream);
+
+/*
  * Zoom DFT on the matrix cores: K bins of the N-point spectrum of every gate,
  * starting at a per-gate bin, without the full transform.  Each gate's
  * decoded rows are shifted so that its window starts at bin 0 and multiplied
@@ -157,6 +177,22 @@ ispl_status ispl_zoom_spectra(ispl_zoom* zoom, const void* samples, const float*
                               int32_t tx_per_pulse, int32_t n_pulses,
                               const int32_t* bin_start, float* spectra, int32_t accumulate,
                               void* stream);
+
+/* ispl_zoom_spectra for the listed gates only (gate lists as for
+ * ispl_integrate_spectra_gates). */
+ispl_status ispl_zoom_spectra_gates(ispl_zoom* zoom, const void* samples, const float* tx_code,
+                                    int32_t tx_per_pulse, int32_t n_pulses,
+                                    const int32_t* bin_start, const int32_t* gate_list,
+                                    const int32_t* gate_count, float* spectra,
+                                    int32_t accumulate, void* stream);
+
+/* Peak of each listed gate's window (Section 3.2's peak search on the zoomed
+ * bins): peak_bin[g] = (bin_start[g] + j) mod N for the lowest j attaining
+ * max_j spectra[g][j]; peak_power[g] = that maximum (NULL: not wanted).
+ * spectra device float [n_gates][n_bins]; other gates untouched. */
+ispl_status ispl_zoom_find_peaks(ispl_zoom* zoom, const float* spectra, const int32_t* bin_start,
+                                 const int32_t* gate_list, const int32_t* gate_count,
+                                 int32_t* peak_bin, float* peak_power, void* stream);
 
 void ispl_zoom_destroy(ispl_zoom* zoom);
 
@@ -193,7 +229,9 @@ ispl_status ispl_net_get_params(ispl_net* net, float* host_params);
 /* features[r][t] from spectra[r][t], device [rows][ISPL_NET_LEN] each. */
 ispl_status ispl_net_features(ispl_net* net, const float* spectra, int32_t rows,
                               float* features, void* stream);
-/* logits[b][t] of features[b][t], device [batch][ISPL_NET_LEN], batch <= max_batch. */
+/* logits[b][t] of features[b][t], device [batch][ISPL_NET_LEN] (16-byte aligned);
+ * precision ISPL_NET_FP32 needs batch <= max_batch (its activations use the
+ * workspace), ISPL_NET_BF16 takes any batch >= 0. */
 ispl_status ispl_net_forward(ispl_net* net, const float* features, int32_t batch,
                              float* logits, int32_t precision, void* stream);
 /* Mean loss (device float [1]) and its gradient (device float [ISPL_NET_PARAMS])
@@ -203,6 +241,75 @@ ispl_status ispl_net_loss_grad(ispl_net* net, const float* features, const float
 /* loss_grad, then one Adam step of learning rate lr. */
 ispl_status ispl_net_train_step(ispl_net* net, const float* features, const float* target_pos,
                                 int32_t batch, float lr, float* loss, void* stream);
+
+/*
+ * Window decision of the learned zoom, from logits [n_gates][ISPL_NET_LEN]
+ * (device, 16-byte aligned).  With T = 1024 coarse bins, S = fine_len / T:
+ *   p = softmax(logits), m = lowest index of the largest logit,
+ *   u = m + sum_d d p[m+d] / sum_d p[m+d], d = -2..2 (indices mod T),
+ *   c = S u, bin_start[g] = (floor(c + 1/2) - window_bins / 2) mod fine_len,
+ *   confidence[g] = sum of p[t] over the t whose fine position S t lies
+ *                   within window_bins / 2 - S of c (circular distance),
+ *   flag[g] = confidence >= threshold.
+ * zoom_list / fallback_list (device int32 [n_gates]) receive the flagged and
+ * the other gates in increasing order, counts[0] / counts[1] (device int32
+ * [2]) their numbers.  confidence may be NULL.  fine_len: a power of two
+ * >= 1024; 2 S < window_bins <= fine_len; 0 < threshold <= 1.  This rule is
+ * the project's (the paper computes every gate at full resolution); all
+ * arithmetic is FP32.
+ */
+ispl_status ispl_net_select(ispl_net* net, const float* logits, int32_t n_gates,
+                            int32_t fine_len, int32_t window_bins, float threshold,
+                            int32_t* bin_start, float* confidence, int32_t* flag,
+                            int32_t* zoom_list, int32_t* fallback_list, int32_t* counts,
+                            void* stream);
+
+/*
+ * Learned zoom: peak frequency of every gate without the full-resolution
+ * spectrum of every gate.  One call runs, on `stream`:
+ *   1. ispl_integrate_spectra at N_c = 1024 (the coarse spectra);
+ *   2. the network's features and BF16 logits;
+ *   3. ispl_net_select with (cfg->fft_len, window_bins, threshold);
+ *   4. ispl_zoom_spectra_gates over the zoomed gates (window_bins bins from
+ *      bin_start, zoom_precision) and ispl_integrate_spectra_gates at
+ *      cfg->fft_len over the fallback gates;
+ *   5. ispl_zoom_find_peaks and ispl_find_plasma_line_gates (full band).
+ * peak_bin[g] / peak_power[g] (device int32 / float [n_gates]; peak_power
+ * may be NULL) then hold every gate's line bin at N = cfg->fft_len.
+ * ispl_lzoom_create: cfg as for ispl_create with code_len <= 1024 and
+ * fft_len >= 1024; window_bins a multiple of 128 with 2 fft_len / 1024 <
+ * window_bins <= fft_len; zoom_precision an ispl_zoom_precision; threshold
+ * in (0, 1].  `net` stays owned by the caller, must outlive the object and
+ * be on cfg->device; its current parameters are used at every call.  The
+ * object owns two contexts, a zoom table and [n_gates] x (3 * 1024 +
+ * window_bins + fft_len) floats of buffers.  Not thread-safe.
+ */
+typedef struct ispl_lzoom ispl_lzoom;
+
+ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t window_bins,
+                              int32_t zoom_precision, float threshold, ispl_lzoom** out);
+void ispl_lzoom_destroy(ispl_lzoom* lzoom);
+ispl_status ispl_lzoom_peaks(ispl_lzoom* lzoom, const void* samples, const float* tx_code,
+                             int32_t tx_per_pulse, int32_t n_pulses, int32_t* peak_bin,
+                             float* peak_power, void* stream);
+
+/* Device pointers to the intermediate results of the last ispl_lzoom_peaks
+ * (owned by the object, valid until it is destroyed; read after the stream
+ * has completed): for diagnostics, tests and accounting of the split. */
+typedef struct {
+  int32_t n_gates, window_bins, fine_len;
+  const float* coarse_spectra;   /* [n_gates][1024] */
+  const float* logits;           /* [n_gates][1024] */
+  const int32_t* bin_start;      /* [n_gates] */
+  const float* confidence;       /* [n_gates] */
+  const int32_t* zoom_list;      /* [n_gates], first counts[0] entries valid */
+  const int32_t* fallback_list;  /* [n_gates], first counts[1] entries valid */
+  const int32_t* counts;         /* [2] */
+  const float* window_spectra;   /* [n_gates][window_bins], zoomed gates' rows */
+  const float* full_spectra;     /* [n_gates][fine_len], fallback gates' rows */
+} ispl_lzoom_buffers;
+
+ispl_status ispl_lzoom_view(const ispl_lzoom* lzoom, ispl_lzoom_buffers* out);
 
 /* Frees the context and its device memory (synchronises its device first).
  * NULL is a no-op. */

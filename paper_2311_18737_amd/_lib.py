@@ -43,6 +43,15 @@ EXPORTED = (
     "ispl_net_forward",
     "ispl_net_loss_grad",
     "ispl_net_train_step",
+    "ispl_integrate_spectra_gates",
+    "ispl_find_plasma_line_gates",
+    "ispl_zoom_spectra_gates",
+    "ispl_zoom_find_peaks",
+    "ispl_net_select",
+    "ispl_lzoom_create",
+    "ispl_lzoom_destroy",
+    "ispl_lzoom_peaks",
+    "ispl_lzoom_view",
     "ispl_plan",
     "ispl_status_string",
     "ispl_last_error",
@@ -62,6 +71,23 @@ class IsplConfig(ctypes.Structure):
         ("sample_type", ctypes.c_int32),
         ("max_pulses", ctypes.c_int32),
         ("device", ctypes.c_int32),
+    ]
+
+
+class IsplLzoomBuffers(ctypes.Structure):
+    _fields_ = [
+        ("n_gates", ctypes.c_int32),
+        ("window_bins", ctypes.c_int32),
+        ("fine_len", ctypes.c_int32),
+        ("coarse_spectra", ctypes.c_void_p),
+        ("logits", ctypes.c_void_p),
+        ("bin_start", ctypes.c_void_p),
+        ("confidence", ctypes.c_void_p),
+        ("zoom_list", ctypes.c_void_p),
+        ("fallback_list", ctypes.c_void_p),
+        ("counts", ctypes.c_void_p),
+        ("window_spectra", ctypes.c_void_p),
+        ("full_spectra", ctypes.c_void_p),
     ]
 
 
@@ -129,6 +155,26 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ispl_net_loss_grad.restype = i32
     lib.ispl_net_train_step.argtypes = [vp, vp, vp, i32, ctypes.c_float, vp, vp]
     lib.ispl_net_train_step.restype = i32
+    lib.ispl_integrate_spectra_gates.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, i32, vp]
+    lib.ispl_integrate_spectra_gates.restype = i32
+    lib.ispl_find_plasma_line_gates.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
+    lib.ispl_find_plasma_line_gates.restype = i32
+    lib.ispl_zoom_spectra_gates.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, i32, vp]
+    lib.ispl_zoom_spectra_gates.restype = i32
+    lib.ispl_zoom_find_peaks.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.ispl_zoom_find_peaks.restype = i32
+    lib.ispl_net_select.argtypes = [vp, vp, i32, i32, i32, ctypes.c_float, vp, vp, vp, vp, vp,
+                                    vp, vp]
+    lib.ispl_net_select.restype = i32
+    lib.ispl_lzoom_create.argtypes = [ctypes.POINTER(IsplConfig), vp, i32, i32, ctypes.c_float,
+                                      ctypes.POINTER(vp)]
+    lib.ispl_lzoom_create.restype = i32
+    lib.ispl_lzoom_destroy.argtypes = [vp]
+    lib.ispl_lzoom_destroy.restype = None
+    lib.ispl_lzoom_peaks.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp]
+    lib.ispl_lzoom_peaks.restype = i32
+    lib.ispl_lzoom_view.argtypes = [vp, ctypes.POINTER(IsplLzoomBuffers)]
+    lib.ispl_lzoom_view.restype = i32
     lib.ispl_plan.argtypes = [ctypes.POINTER(IsplConfig), i32, ctypes.POINTER(i32),
                               ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.ispl_plan.restype = i32

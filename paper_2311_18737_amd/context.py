@@ -47,9 +47,25 @@ def _stream_handle(stream, device) -> int:
     return int(stream.cuda_stream)
 
 
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
 def _require(cond: bool, msg: str) -> None:
     if not cond:
         raise ValueError(msg)
+
+
+def _gate_list(gates, n_gates: int, device):
+    """(list, count) device int32 tensors of a gate-list call."""
+    _require(isinstance(gates, (tuple, list)) and len(gates) == 2,
+             "gates must be a (gate_list, gate_count) pair of tensors")
+    lst, cnt = gates
+    _require(lst.device == device and lst.dtype == torch.int32 and lst.is_contiguous()
+             and tuple(lst.shape) == (n_gates,), "gate_list must be int32 [n_gates] on the device")
+    _require(cnt.device == device and cnt.dtype == torch.int32 and cnt.numel() >= 1,
+             "gate_count must be an int32 tensor on the device")
+    return ctypes.c_void_p(lst.data_ptr()), ctypes.c_void_p(cnt.data_ptr())
 
 
 class Context:
@@ -113,12 +129,15 @@ class Context:
 
     def integrate_spectra(self, samples: torch.Tensor, tx: torch.Tensor, *,
                           out: Optional[torch.Tensor] = None, accumulate: bool = False,
-                          stream=None) -> torch.Tensor:
+                          gates=None, stream=None) -> torch.Tensor:
         """S[g][k] = sum_p |FFT_N(conj(c_p) * gate window)|^2 (ispl_integrate_spectra).
 
         samples: [P][pulse_stride] complex64, or int16 [P][pulse_stride][2].
         tx: complex64 [P][L] (one code per pulse) or [L] / [1][L] (shared).
         out: float32 [G][N]; allocated when None (accumulate needs it given).
+        gates: optional (gate_list, gate_count) int32 device tensors; only those
+        gates' rows are computed (ispl_integrate_spectra_gates), other rows of
+        `out` are untouched (zero when `out` is allocated here).
         """
         h = self._handle()
         n_pulses = self._check_samples(samples)
@@ -131,24 +150,34 @@ class Context:
         _require(not per_pulse or tx.shape[0] == n_pulses, "tx rows must be 1 or n_pulses")
         if out is None:
             _require(not accumulate, "accumulate=True needs `out`")
-            out = torch.empty((self.n_gates, self.fft_len), dtype=torch.float32,
-                              device=self.device)
+            alloc = torch.zeros if gates is not None else torch.empty
+            out = alloc((self.n_gates, self.fft_len), dtype=torch.float32, device=self.device)
         _require(out.device == self.device and out.dtype == torch.float32 and out.is_contiguous()
                  and tuple(out.shape) == (self.n_gates, self.fft_len),
                  "out must be contiguous float32 [n_gates][fft_len] on the device")
-        st = self._lib.ispl_integrate_spectra(
-            h, ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(tx.data_ptr()),
-            int(per_pulse), n_pulses, ctypes.c_void_p(out.data_ptr()), int(bool(accumulate)),
-            ctypes.c_void_p(_stream_handle(stream, self.device)))
-        check(st, "ispl_integrate_spectra")
+        sh = ctypes.c_void_p(_stream_handle(stream, self.device))
+        if gates is None:
+            st = self._lib.ispl_integrate_spectra(
+                h, ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(tx.data_ptr()),
+                int(per_pulse), n_pulses, ctypes.c_void_p(out.data_ptr()), int(bool(accumulate)),
+                sh)
+            check(st, "ispl_integrate_spectra")
+        else:
+            gl, gc = _gate_list(gates, self.n_gates, self.device)
+            st = self._lib.ispl_integrate_spectra_gates(
+                h, ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(tx.data_ptr()),
+                int(per_pulse), n_pulses, gl, gc, ctypes.c_void_p(out.data_ptr()),
+                int(bool(accumulate)), sh)
+            check(st, "ispl_integrate_spectra_gates")
         return out
 
     def find_plasma_line(self, spectra: torch.Tensor, bin_lo: int = 0,
                          bin_hi: Optional[int] = None, *, want_power: bool = True,
                          out_bins: Optional[torch.Tensor] = None,
-                         out_power: Optional[torch.Tensor] = None, stream=None):
+                         out_power: Optional[torch.Tensor] = None, gates=None, stream=None):
         """Per-gate peak bin (lowest bin among equal maxima) over [bin_lo, bin_hi),
-        wrapping through N when bin_lo > bin_hi (ispl_find_plasma_line)."""
+        wrapping through N when bin_lo > bin_hi (ispl_find_plasma_line); with
+        `gates`, only the listed gates (ispl_find_plasma_line_gates)."""
         h = self._handle()
         if bin_hi is None:
             bin_hi = self.fft_len
@@ -161,11 +190,18 @@ class Context:
         if want_power and out_power is None:
             out_power = torch.empty(self.n_gates, dtype=torch.float32, device=self.device)
         pp = ctypes.c_void_p(out_power.data_ptr()) if want_power else ctypes.c_void_p(0)
-        st = self._lib.ispl_find_plasma_line(
-            h, ctypes.c_void_p(spectra.data_ptr()), int(bin_lo), int(bin_hi),
-            ctypes.c_void_p(out_bins.data_ptr()), pp,
-            ctypes.c_void_p(_stream_handle(stream, self.device)))
-        check(st, "ispl_find_plasma_line")
+        sh = ctypes.c_void_p(_stream_handle(stream, self.device))
+        if gates is None:
+            st = self._lib.ispl_find_plasma_line(
+                h, ctypes.c_void_p(spectra.data_ptr()), int(bin_lo), int(bin_hi),
+                ctypes.c_void_p(out_bins.data_ptr()), pp, sh)
+            check(st, "ispl_find_plasma_line")
+        else:
+            gl, gc = _gate_list(gates, self.n_gates, self.device)
+            st = self._lib.ispl_find_plasma_line_gates(
+                h, ctypes.c_void_p(spectra.data_ptr()), int(bin_lo), int(bin_hi), gl, gc,
+                ctypes.c_void_p(out_bins.data_ptr()), pp, sh)
+            check(st, "ispl_find_plasma_line_gates")
         return out_bins, (out_power if want_power else None)
 
 
@@ -208,8 +244,9 @@ class Zoom:
 
     def spectra(self, samples: torch.Tensor, tx: torch.Tensor, bin_start: torch.Tensor, *,
                 out: Optional[torch.Tensor] = None, accumulate: bool = False,
-                stream=None) -> torch.Tensor:
-        """out[g][j] = sum_p |DFT of the decoded gate window at bin bin_start[g] + j|^2."""
+                gates=None, stream=None) -> torch.Tensor:
+        """out[g][j] = sum_p |DFT of the decoded gate window at bin bin_start[g] + j|^2;
+        with `gates`, only the listed gates (ispl_zoom_spectra_gates)."""
         if self._h is None:
             raise RuntimeError("zoom is closed")
         ctx = self.ctx
@@ -226,24 +263,50 @@ class Zoom:
                  "bin_start must be contiguous int32 [n_gates] on the device")
         if out is None:
             _require(not accumulate, "accumulate=True needs `out`")
-            out = torch.empty((ctx.n_gates, self.n_bins), dtype=torch.float32, device=ctx.device)
+            alloc = torch.zeros if gates is not None else torch.empty
+            out = alloc((ctx.n_gates, self.n_bins), dtype=torch.float32, device=ctx.device)
         _require(out.device == ctx.device and out.dtype == torch.float32 and out.is_contiguous()
                  and tuple(out.shape) == (ctx.n_gates, self.n_bins),
                  "out must be contiguous float32 [n_gates][n_bins] on the device")
-        st = self._lib.ispl_zoom_spectra(
-            self._h, ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(tx.data_ptr()),
-            int(per_pulse), n_pulses, ctypes.c_void_p(bin_start.data_ptr()),
-            ctypes.c_void_p(out.data_ptr()), int(bool(accumulate)),
-            ctypes.c_void_p(_stream_handle(stream, ctx.device)))
-        check(st, "ispl_zoom_spectra")
+        sh = ctypes.c_void_p(_stream_handle(stream, ctx.device))
+        if gates is None:
+            st = self._lib.ispl_zoom_spectra(
+                self._h, ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(tx.data_ptr()),
+                int(per_pulse), n_pulses, ctypes.c_void_p(bin_start.data_ptr()),
+                ctypes.c_void_p(out.data_ptr()), int(bool(accumulate)), sh)
+            check(st, "ispl_zoom_spectra")
+        else:
+            gl, gc = _gate_list(gates, ctx.n_gates, ctx.device)
+            st = self._lib.ispl_zoom_spectra_gates(
+                self._h, ctypes.c_void_p(samples.data_ptr()), ctypes.c_void_p(tx.data_ptr()),
+                int(per_pulse), n_pulses, ctypes.c_void_p(bin_start.data_ptr()), gl, gc,
+                ctypes.c_void_p(out.data_ptr()), int(bool(accumulate)), sh)
+            check(st, "ispl_zoom_spectra_gates")
         return out
+
+    def find_peaks(self, spectra: torch.Tensor, bin_start: torch.Tensor, gates, *,
+                   out_bins: Optional[torch.Tensor] = None,
+                   out_power: Optional[torch.Tensor] = None, stream=None):
+        """Peak bin (bin_start + lowest argmax) of each listed gate's window
+        (ispl_zoom_find_peaks); other gates' entries are untouched."""
+        ctx = self.ctx
+        _require(spectra.device == ctx.device and spectra.dtype == torch.float32
+                 and spectra.is_contiguous() and tuple(spectra.shape) == (ctx.n_gates, self.n_bins),
+                 "spectra must be contiguous float32 [n_gates][n_bins] on the device")
+        _require(bin_start.device == ctx.device and bin_start.dtype == torch.int32
+                 and tuple(bin_start.shape) == (ctx.n_gates,), "bin_start must be int32 [n_gates]")
+        if out_bins is None:
+            out_bins = torch.full((ctx.n_gates,), -1, dtype=torch.int32, device=ctx.device)
+        if out_power is None:
+            out_power = torch.zeros(ctx.n_gates, dtype=torch.float32, device=ctx.device)
+        gl, gc = _gate_list(gates, ctx.n_gates, ctx.device)
+        check(self._lib.ispl_zoom_find_peaks(
+            self._h, _ptr(spectra), _ptr(bin_start), gl, gc, _ptr(out_bins), _ptr(out_power),
+            ctypes.c_void_p(_stream_handle(stream, ctx.device))), "ispl_zoom_find_peaks")
+        return out_bins, out_power
 
 
 _NET_PRECISIONS = {"fp32": _lib.ISPL_NET_FP32, "bf16": _lib.ISPL_NET_BF16}
-
-
-def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
-    return ctypes.c_void_p(t.data_ptr())
 
 
 class Net:
@@ -337,3 +400,109 @@ class Net:
                                             ctypes.c_void_p(_stream_handle(stream, self.device))),
               "ispl_net_train_step")
         return loss
+
+    def select(self, logits: torch.Tensor, fine_len: int, window_bins: int, threshold: float,
+               stream=None) -> dict:
+        """Window decision per gate (ispl_net_select): bin_start, confidence, flag,
+        zoom_list, fallback_list and counts = [n_zoom, n_fallback], all device tensors."""
+        rows = self._rows(logits, "logits")
+        dev = self.device
+        out = {k: torch.empty(rows, dtype=torch.int32, device=dev)
+               for k in ("bin_start", "flag", "zoom_list", "fallback_list")}
+        out["confidence"] = torch.empty(rows, dtype=torch.float32, device=dev)
+        out["counts"] = torch.empty(2, dtype=torch.int32, device=dev)
+        check(self._lib.ispl_net_select(
+            self._h, _ptr(logits), rows, int(fine_len), int(window_bins), float(threshold),
+            _ptr(out["bin_start"]), _ptr(out["confidence"]), _ptr(out["flag"]),
+            _ptr(out["zoom_list"]), _ptr(out["fallback_list"]), _ptr(out["counts"]),
+            ctypes.c_void_p(_stream_handle(stream, dev))), "ispl_net_select")
+        return out
+
+
+class _DeviceArray:
+    """A borrowed device array, viewed as a torch tensor via __cuda_array_interface__."""
+
+    def __init__(self, ptr: int, shape, typestr: str, owner):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (int(ptr), False), "version": 2, "strides": None}
+        self._owner = owner
+
+
+class LearnedZoom:
+    """Peak frequency of every gate through the learned zoom (ispl_lzoom_*):
+    coarse spectra, network, window decision, zoom DFT for confident gates and
+    the full-resolution fallback for the others.  `net` must stay open."""
+
+    def __init__(self, net: Net, *, code_len: int, fft_len: int, n_gates: int,
+                 gate_step: int = 25, first_gate: int = 0, pulse_stride: Optional[int] = None,
+                 sample_type: str = "c64", max_pulses: int, window_bins: int = 256,
+                 precision: str = "fp16x3", threshold: float = 0.9):
+        if precision not in _ZOOM_PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(_ZOOM_PRECISIONS)}")
+        self._lib = load_library()
+        self.net = net
+        self.device = net.device
+        self.cfg = make_config(code_len=code_len, fft_len=fft_len, n_gates=n_gates,
+                               gate_step=gate_step, first_gate=first_gate,
+                               pulse_stride=pulse_stride, sample_type=sample_type,
+                               max_pulses=max_pulses, device=net.device.index or 0)
+        self.sample_type = sample_type
+        self.window_bins = window_bins
+        self.threshold = threshold
+        h = ctypes.c_void_p()
+        check(self._lib.ispl_lzoom_create(ctypes.byref(self.cfg), net._h, int(window_bins),
+                                          _ZOOM_PRECISIONS[precision], float(threshold),
+                                          ctypes.byref(h)), "ispl_lzoom_create")
+        self._h = h
+        # geometry checks of the samples reuse a context-like view
+        self.code_len, self.fft_len, self.n_gates = code_len, fft_len, n_gates
+        self.pulse_stride = self.cfg.pulse_stride
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ispl_lzoom_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def peaks(self, samples: torch.Tensor, tx: torch.Tensor, *,
+              out_bins: Optional[torch.Tensor] = None, out_power: Optional[torch.Tensor] = None,
+              stream=None):
+        """(peak_bin int32 [G], peak_power float32 [G]) at N = fft_len."""
+        if self._h is None:
+            raise RuntimeError("learned zoom is closed")
+        n_pulses = Context._check_samples(self, samples)
+        _require(tx.device == self.device and tx.is_contiguous() and tx.dtype == torch.complex64,
+                 "tx must be contiguous complex64 on the device")
+        if tx.dim() == 1:
+            tx = tx.unsqueeze(0)
+        _require(tx.dim() == 2 and tx.shape[1] == self.code_len, "tx must be [P or 1][code_len]")
+        per_pulse = tx.shape[0] != 1
+        _require(not per_pulse or tx.shape[0] == n_pulses, "tx rows must be 1 or n_pulses")
+        if out_bins is None:
+            out_bins = torch.empty(self.n_gates, dtype=torch.int32, device=self.device)
+        if out_power is None:
+            out_power = torch.empty(self.n_gates, dtype=torch.float32, device=self.device)
+        check(self._lib.ispl_lzoom_peaks(
+            self._h, _ptr(samples), _ptr(tx), int(per_pulse), n_pulses, _ptr(out_bins),
+            _ptr(out_power), ctypes.c_void_p(_stream_handle(stream, self.device))),
+            "ispl_lzoom_peaks")
+        return out_bins, out_power
+
+    def view(self) -> dict:
+        """Borrowed tensors over the intermediate results of the last peaks()
+        call (valid while this object lives; synchronise the stream first)."""
+        b = _lib.IsplLzoomBuffers()
+        check(self._lib.ispl_lzoom_view(self._h, ctypes.byref(b)), "ispl_lzoom_view")
+        G, K, N, T = b.n_gates, b.window_bins, b.fine_len, Net.LEN
+        spec = {"coarse_spectra": ((G, T), "<f4"), "logits": ((G, T), "<f4"),
+                "bin_start": ((G,), "<i4"), "confidence": ((G,), "<f4"),
+                "zoom_list": ((G,), "<i4"), "fallback_list": ((G,), "<i4"),
+                "counts": ((2,), "<i4"), "window_spectra": ((G, K), "<f4"),
+                "full_spectra": ((G, N), "<f4")}
+        return {k: torch.as_tensor(_DeviceArray(getattr(b, k), shp, ts, self), device=self.device)
+                for k, (shp, ts) in spec.items()}

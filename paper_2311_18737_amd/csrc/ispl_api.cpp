@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime_api.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -351,9 +352,10 @@ void ispl_destroy(ispl_ctx* ctx) {
   delete ctx;
 }
 
-ispl_status ispl_integrate_spectra(ispl_ctx* ctx, const void* samples, const float* tx_code,
-                                   int32_t tx_per_pulse, int32_t n_pulses, float* spectra,
-                                   int32_t accumulate, void* stream) {
+static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const float* tx_code,
+                                  int32_t tx_per_pulse, int32_t n_pulses,
+                                  const int32_t* gate_list, const int32_t* gate_count,
+                                  float* spectra, int32_t accumulate, void* stream) {
   if (!ctx) return fail(ISPL_ERR_INVALID_ARG, "context is NULL");
   const ispl_config& c = ctx->cfg;
   if (n_pulses < 0 || n_pulses > c.max_pulses)
@@ -378,7 +380,9 @@ ispl_status ispl_integrate_spectra(ispl_ctx* ctx, const void* samples, const flo
   hipError_t e;
   if (n_pulses == 0) {
     if (!accumulate) {
-      e = ispl::launch_fill_zero(spectra, elems, s);
+      e = gate_list ? ispl::launch_fill_zero_rows(spectra, c.n_gates, c.fft_len, gate_list,
+                                                  gate_count, s)
+                    : ispl::launch_fill_zero(spectra, elems, s);
       if (e != hipSuccess) return hip_fail(e, "fill_zero launch");
     }
     return ok();
@@ -407,13 +411,41 @@ ispl_status ispl_integrate_spectra(ispl_ctx* ctx, const void* samples, const flo
   a.accumulate = accumulate;
   a.sample_type = c.sample_type;
   a.waves_per_block = pl.rw;
+  a.gate_list = gate_list;
+  a.gate_count = gate_count;
   e = ispl::launch_fused(a, s);
   if (e != hipSuccess) return hip_fail(e, "fused launch");
   if (pl.chunks > 1) {
-    e = ispl::launch_reduce_chunks(ctx->partial, spectra, elems, pl.chunks, accumulate, s);
+    e = ispl::launch_reduce_chunks(ctx->partial, spectra, elems, pl.chunks, accumulate,
+                                   c.fft_len, gate_list, gate_count, s);
     if (e != hipSuccess) return hip_fail(e, "chunk reduce launch");
   }
   return ok();
+}
+
+static ispl_status check_gate_list(const int32_t* gate_list, const int32_t* gate_count) {
+  if (!gate_list || !gate_count) return fail(ISPL_ERR_INVALID_ARG, "gate_list or gate_count is NULL");
+  if (misaligned(gate_list, 4) || misaligned(gate_count, 4))
+    return fail(ISPL_ERR_INVALID_ARG, "gate_list or gate_count not 4-byte aligned");
+  return ISPL_OK;
+}
+
+ispl_status ispl_integrate_spectra(ispl_ctx* ctx, const void* samples, const float* tx_code,
+                                   int32_t tx_per_pulse, int32_t n_pulses, float* spectra,
+                                   int32_t accumulate, void* stream) {
+  return integrate_impl(ctx, samples, tx_code, tx_per_pulse, n_pulses, nullptr, nullptr, spectra,
+                        accumulate, stream);
+}
+
+ispl_status ispl_integrate_spectra_gates(ispl_ctx* ctx, const void* samples,
+                                         const float* tx_code, int32_t tx_per_pulse,
+                                         int32_t n_pulses, const int32_t* gate_list,
+                                         const int32_t* gate_count, float* spectra,
+                                         int32_t accumulate, void* stream) {
+  const ispl_status st = check_gate_list(gate_list, gate_count);
+  if (st != ISPL_OK) return st;
+  return integrate_impl(ctx, samples, tx_code, tx_per_pulse, n_pulses, gate_list, gate_count,
+                        spectra, accumulate, stream);
 }
 
 ispl_status ispl_zoom_create(ispl_ctx* ctx, int32_t n_bins, int32_t precision,
@@ -472,9 +504,10 @@ void ispl_zoom_destroy(ispl_zoom* z) {
   delete z;
 }
 
-ispl_status ispl_zoom_spectra(ispl_zoom* z, const void* samples, const float* tx_code,
-                              int32_t tx_per_pulse, int32_t n_pulses, const int32_t* bin_start,
-                              float* spectra, int32_t accumulate, void* stream) {
+static ispl_status zoom_impl(ispl_zoom* z, const void* samples, const float* tx_code,
+                             int32_t tx_per_pulse, int32_t n_pulses, const int32_t* bin_start,
+                             const int32_t* gate_list, const int32_t* gate_count, float* spectra,
+                             int32_t accumulate, void* stream) {
   if (!z) return fail(ISPL_ERR_INVALID_ARG, "zoom is NULL");
   const ispl_config& c = z->ctx->cfg;
   if (n_pulses < 0 || n_pulses > c.max_pulses)
@@ -496,7 +529,9 @@ ispl_status ispl_zoom_spectra(ispl_zoom* z, const void* samples, const float* tx
   if (n_pulses == 0) {
     if (!accumulate) {
       const hipError_t e =
-          ispl::launch_fill_zero(spectra, static_cast<int64_t>(c.n_gates) * z->n_bins, s);
+          gate_list ? ispl::launch_fill_zero_rows(spectra, c.n_gates, z->n_bins, gate_list,
+                                                  gate_count, s)
+                    : ispl::launch_fill_zero(spectra, static_cast<int64_t>(c.n_gates) * z->n_bins, s);
       if (e != hipSuccess) return hip_fail(e, "fill_zero launch");
     }
     return ok();
@@ -522,8 +557,48 @@ ispl_status ispl_zoom_spectra(ispl_zoom* z, const void* samples, const float* tx
   a.accumulate = accumulate;
   a.sample_type = c.sample_type;
   a.precision = z->precision;
+  a.gate_list = gate_list;
+  a.gate_count = gate_count;
   const hipError_t e = ispl::launch_zoom(a, s);
   if (e != hipSuccess) return hip_fail(e, "zoom launch");
+  return ok();
+}
+
+ispl_status ispl_zoom_spectra(ispl_zoom* z, const void* samples, const float* tx_code,
+                              int32_t tx_per_pulse, int32_t n_pulses, const int32_t* bin_start,
+                              float* spectra, int32_t accumulate, void* stream) {
+  return zoom_impl(z, samples, tx_code, tx_per_pulse, n_pulses, bin_start, nullptr, nullptr,
+                   spectra, accumulate, stream);
+}
+
+ispl_status ispl_zoom_spectra_gates(ispl_zoom* z, const void* samples, const float* tx_code,
+                                    int32_t tx_per_pulse, int32_t n_pulses,
+                                    const int32_t* bin_start, const int32_t* gate_list,
+                                    const int32_t* gate_count, float* spectra, int32_t accumulate,
+                                    void* stream) {
+  const ispl_status st = check_gate_list(gate_list, gate_count);
+  if (st != ISPL_OK) return st;
+  return zoom_impl(z, samples, tx_code, tx_per_pulse, n_pulses, bin_start, gate_list, gate_count,
+                   spectra, accumulate, stream);
+}
+
+ispl_status ispl_zoom_find_peaks(ispl_zoom* z, const float* spectra, const int32_t* bin_start,
+                                 const int32_t* gate_list, const int32_t* gate_count,
+                                 int32_t* peak_bin, float* peak_power, void* stream) {
+  if (!z) return fail(ISPL_ERR_INVALID_ARG, "zoom is NULL");
+  const ispl_status st = check_gate_list(gate_list, gate_count);
+  if (st != ISPL_OK) return st;
+  if (!spectra || !bin_start || !peak_bin)
+    return fail(ISPL_ERR_INVALID_ARG, "spectra, bin_start or peak_bin is NULL");
+  if (misaligned(spectra, 4) || misaligned(bin_start, 4) || misaligned(peak_bin, 4) ||
+      misaligned(peak_power, 4))
+    return fail(ISPL_ERR_INVALID_ARG, "pointer not 4-byte aligned");
+  const ispl_config& c = z->ctx->cfg;
+  DeviceGuard guard(c.device);
+  const hipError_t e =
+      ispl::launch_window_peak(spectra, c.n_gates, z->n_bins, c.fft_len, bin_start, gate_list,
+                               gate_count, peak_bin, peak_power, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "window peak launch");
   return ok();
 }
 
@@ -647,10 +722,12 @@ ispl_status ispl_net_features(ispl_net* n, const float* spectra, int32_t rows, f
 ispl_status ispl_net_forward(ispl_net* n, const float* features, int32_t batch, float* logits,
                              int32_t precision, void* stream) {
   if (!n) return fail(ISPL_ERR_INVALID_ARG, "NULL net");
-  if (batch < 0 || batch > n->max_batch)
-    return fail(ISPL_ERR_INVALID_ARG, "batch %d outside [0, max_batch %d]", batch, n->max_batch);
   if (precision != ISPL_NET_FP32 && precision != ISPL_NET_BF16)
     return fail(ISPL_ERR_INVALID_ARG, "unknown precision %d", precision);
+  // the FP32 forward stages activations in the workspace; BF16 keeps them in LDS
+  const int32_t limit = precision == ISPL_NET_FP32 ? n->max_batch : INT32_MAX;
+  if (batch < 0 || batch > limit)
+    return fail(ISPL_ERR_INVALID_ARG, "batch %d outside [0, %d]", batch, limit);
   if (batch == 0) return ok();  // empty tensors may carry NULL pointers
   if (!features || !logits) return fail(ISPL_ERR_INVALID_ARG, "NULL argument");
   if (misaligned(features, 16) || misaligned(logits, 16))
@@ -702,9 +779,9 @@ ispl_status ispl_net_train_step(ispl_net* n, const float* features, const float*
   return ok();
 }
 
-ispl_status ispl_find_plasma_line(ispl_ctx* ctx, const float* spectra, int32_t bin_lo,
-                                  int32_t bin_hi, int32_t* peak_bin, float* peak_power,
-                                  void* stream) {
+static ispl_status peak_impl(ispl_ctx* ctx, const float* spectra, int32_t bin_lo,
+                             int32_t bin_hi, const int32_t* gate_list, const int32_t* gate_count,
+                             int32_t* peak_bin, float* peak_power, void* stream) {
   if (!ctx) return fail(ISPL_ERR_INVALID_ARG, "context is NULL");
   const ispl_config& c = ctx->cfg;
   if (!spectra || !peak_bin) return fail(ISPL_ERR_INVALID_ARG, "spectra or peak_bin is NULL");
@@ -714,9 +791,240 @@ ispl_status ispl_find_plasma_line(ispl_ctx* ctx, const float* spectra, int32_t b
     return fail(ISPL_ERR_INVALID_ARG, "band [%d, %d) invalid for fft_len %d", bin_lo, bin_hi,
                 c.fft_len);
   DeviceGuard guard(c.device);
-  const hipError_t e = ispl::launch_peak(spectra, c.n_gates, c.fft_len, bin_lo, bin_hi,
-                                         peak_bin, peak_power, static_cast<hipStream_t>(stream));
+  const hipError_t e =
+      ispl::launch_peak(spectra, c.n_gates, c.fft_len, bin_lo, bin_hi, peak_bin, peak_power,
+                        gate_list, gate_count, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "peak launch");
+  return ok();
+}
+
+ispl_status ispl_find_plasma_line(ispl_ctx* ctx, const float* spectra, int32_t bin_lo,
+                                  int32_t bin_hi, int32_t* peak_bin, float* peak_power,
+                                  void* stream) {
+  return peak_impl(ctx, spectra, bin_lo, bin_hi, nullptr, nullptr, peak_bin, peak_power, stream);
+}
+
+ispl_status ispl_find_plasma_line_gates(ispl_ctx* ctx, const float* spectra, int32_t bin_lo,
+                                        int32_t bin_hi, const int32_t* gate_list,
+                                        const int32_t* gate_count, int32_t* peak_bin,
+                                        float* peak_power, void* stream) {
+  const ispl_status st = check_gate_list(gate_list, gate_count);
+  if (st != ISPL_OK) return st;
+  return peak_impl(ctx, spectra, bin_lo, bin_hi, gate_list, gate_count, peak_bin, peak_power,
+                   stream);
+}
+
+static ispl_status check_window(int32_t fine_len, int32_t window_bins, float threshold) {
+  if (fine_len < ispl::NET_LEN || fine_len % ispl::NET_LEN != 0 || !is_pow2(fine_len))
+    return fail(ISPL_ERR_INVALID_ARG, "fine_len %d: need a power of two >= %d", fine_len,
+                ispl::NET_LEN);
+  const int32_t S = fine_len / ispl::NET_LEN;
+  if (window_bins < 1 || window_bins > fine_len || window_bins / 2 <= S)
+    return fail(ISPL_ERR_INVALID_ARG, "window_bins %d: need 2 * %d < window_bins <= %d",
+                window_bins, S, fine_len);
+  if (!(threshold > 0.f && threshold <= 1.f))
+    return fail(ISPL_ERR_INVALID_ARG, "threshold must lie in (0, 1]");
+  return ISPL_OK;
+}
+
+static void bf16_table_ready(ispl_net* n, hipStream_t s, hipError_t* e) {
+  *e = hipSuccess;
+  if (n->bf16_stale) {
+    *e = ispl::launch_net_prep_bf16(n->w.params, n->bf16_weights, s);
+    if (*e == hipSuccess) n->bf16_stale = false;
+  }
+}
+
+ispl_status ispl_net_select(ispl_net* n, const float* logits, int32_t n_gates, int32_t fine_len,
+                            int32_t window_bins, float threshold, int32_t* bin_start,
+                            float* confidence, int32_t* flag, int32_t* zoom_list,
+                            int32_t* fallback_list, int32_t* counts, void* stream) {
+  if (!n) return fail(ISPL_ERR_INVALID_ARG, "NULL net");
+  ispl_status st = check_window(fine_len, window_bins, threshold);
+  if (st != ISPL_OK) return st;
+  if (n_gates < 1) return fail(ISPL_ERR_INVALID_ARG, "n_gates %d < 1", n_gates);
+  if (!logits || !bin_start || !flag || !zoom_list || !fallback_list || !counts)
+    return fail(ISPL_ERR_INVALID_ARG, "NULL argument");
+  if (misaligned(logits, 16)) return fail(ISPL_ERR_INVALID_ARG, "logits must be 16-byte aligned");
+  if (misaligned(bin_start, 4) || misaligned(confidence, 4) || misaligned(flag, 4) ||
+      misaligned(zoom_list, 4) || misaligned(fallback_list, 4) || misaligned(counts, 4))
+    return fail(ISPL_ERR_INVALID_ARG, "pointer not 4-byte aligned");
+  DeviceGuard guard(n->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = ispl::launch_select_windows(logits, n_gates, fine_len, window_bins, threshold,
+                                             bin_start, confidence, flag, s);
+  if (e == hipSuccess)
+    e = ispl::launch_compact_lists(flag, n_gates, zoom_list, fallback_list, counts, s);
+  if (e != hipSuccess) return hip_fail(e, "select launch");
+  return ok();
+}
+
+}  // extern "C"
+
+struct ispl_lzoom {
+  ispl_ctx* coarse;
+  ispl_ctx* fine;
+  ispl_zoom* zoom;
+  ispl_net* net;
+  int32_t n_gates;
+  int32_t window_bins;
+  float threshold;
+  float* coarse_spectra;  // [G][1024]
+  float* features;        // [G][1024]
+  float* logits;          // [G][1024]
+  float* confidence;      // [G]
+  float* window_spectra;  // [G][K]
+  float* full_spectra;    // [G][N]
+  int32_t* bin_start;     // [G]
+  int32_t* flag;          // [G]
+  int32_t* zoom_list;     // [G]
+  int32_t* fallback_list; // [G]
+  int32_t* counts;        // [2]: zoomed, fallback
+};
+
+namespace {
+
+void lzoom_free(ispl_lzoom* z) {
+  void* bufs[] = {z->coarse_spectra, z->features, z->logits, z->confidence, z->window_spectra,
+                  z->full_spectra, z->bin_start, z->flag, z->zoom_list, z->fallback_list,
+                  z->counts};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (z->zoom) ispl_zoom_destroy(z->zoom);
+  if (z->fine) ispl_destroy(z->fine);
+  if (z->coarse) ispl_destroy(z->coarse);
+}
+
+}  // namespace
+
+extern "C" {
+
+ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t window_bins,
+                              int32_t zoom_precision, float threshold, ispl_lzoom** out) {
+  if (!out) return fail(ISPL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!net) return fail(ISPL_ERR_INVALID_ARG, "NULL net");
+  ispl_status st = validate_config(cfg);
+  if (st != ISPL_OK) return st;
+  if (cfg->device != net->device)
+    return fail(ISPL_ERR_INVALID_ARG, "net is on device %d, config on %d", net->device,
+                cfg->device);
+  if (cfg->code_len > ispl::NET_LEN)
+    return fail(ISPL_ERR_UNSUPPORTED, "code_len %d > %d: the coarse spectrum would truncate it",
+                cfg->code_len, ispl::NET_LEN);
+  st = check_window(cfg->fft_len, window_bins, threshold);
+  if (st != ISPL_OK) return st;
+  ispl_lzoom* z = new (std::nothrow) ispl_lzoom{};
+  if (!z) return fail(ISPL_ERR_OUT_OF_MEMORY, "host allocation");
+  z->net = net;
+  z->n_gates = cfg->n_gates;
+  z->window_bins = window_bins;
+  z->threshold = threshold;
+  ispl_config cc = *cfg;
+  cc.fft_len = ispl::NET_LEN;
+  st = ispl_create(&cc, &z->coarse);
+  if (st == ISPL_OK) st = ispl_create(cfg, &z->fine);
+  if (st == ISPL_OK) st = ispl_zoom_create(z->fine, window_bins, zoom_precision, &z->zoom);
+  if (st != ISPL_OK) {
+    const std::string why = g_last_error;
+    lzoom_free(z);
+    delete z;
+    return fail(st, "%s", why.c_str());
+  }
+  DeviceGuard guard(cfg->device);
+  const int64_t G = cfg->n_gates;
+  struct {
+    void** p;
+    int64_t bytes;
+  } want[] = {{reinterpret_cast<void**>(&z->coarse_spectra), 4 * G * ispl::NET_LEN},
+              {reinterpret_cast<void**>(&z->features), 4 * G * ispl::NET_LEN},
+              {reinterpret_cast<void**>(&z->logits), 4 * G * ispl::NET_LEN},
+              {reinterpret_cast<void**>(&z->confidence), 4 * G},
+              {reinterpret_cast<void**>(&z->window_spectra), 4 * G * window_bins},
+              {reinterpret_cast<void**>(&z->full_spectra), 4 * G * cfg->fft_len},
+              {reinterpret_cast<void**>(&z->bin_start), 4 * G},
+              {reinterpret_cast<void**>(&z->flag), 4 * G},
+              {reinterpret_cast<void**>(&z->zoom_list), 4 * G},
+              {reinterpret_cast<void**>(&z->fallback_list), 4 * G},
+              {reinterpret_cast<void**>(&z->counts), 8}};
+  for (auto& w : want) {
+    const hipError_t e = hipMalloc(w.p, static_cast<size_t>(w.bytes));
+    if (e != hipSuccess) {
+      lzoom_free(z);
+      delete z;
+      return fail(ISPL_ERR_OUT_OF_MEMORY, "learned-zoom buffers: %s", hipGetErrorString(e));
+    }
+  }
+  *out = z;
+  return ok();
+}
+
+void ispl_lzoom_destroy(ispl_lzoom* z) {
+  if (!z) return;
+  {
+    DeviceGuard guard(z->fine ? z->fine->cfg.device : 0);
+    (void)hipDeviceSynchronize();
+    lzoom_free(z);
+  }
+  delete z;
+}
+
+ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx_code,
+                             int32_t tx_per_pulse, int32_t n_pulses, int32_t* peak_bin,
+                             float* peak_power, void* stream) {
+  if (!z) return fail(ISPL_ERR_INVALID_ARG, "learned zoom is NULL");
+  if (!peak_bin) return fail(ISPL_ERR_INVALID_ARG, "peak_bin is NULL");
+  if (misaligned(peak_bin, 4) || misaligned(peak_power, 4))
+    return fail(ISPL_ERR_INVALID_ARG, "peak_bin or peak_power not 4-byte aligned");
+  const ispl_config& c = z->fine->cfg;
+  const int32_t G = z->n_gates;
+  DeviceGuard guard(c.device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // coarse spectra of every gate (the plain path at N = 1024)
+  ispl_status st = integrate_impl(z->coarse, samples, tx_code, tx_per_pulse, n_pulses, nullptr,
+                                  nullptr, z->coarse_spectra, 0, stream);
+  if (st != ISPL_OK) return st;
+  // network: features, BF16 logits, windows and the two gate lists
+  hipError_t e = ispl::launch_net_features(z->coarse_spectra, G, z->features, s);
+  if (e == hipSuccess) bf16_table_ready(z->net, s, &e);
+  if (e == hipSuccess)
+    e = ispl::launch_net_forward_bf16(z->net->bf16_weights, z->features, G, z->logits, s);
+  if (e == hipSuccess)
+    e = ispl::launch_select_windows(z->logits, G, c.fft_len, z->window_bins, z->threshold,
+                                    z->bin_start, z->confidence, z->flag, s);
+  if (e == hipSuccess)
+    e = ispl::launch_compact_lists(z->flag, G, z->zoom_list, z->fallback_list, z->counts, s);
+  if (e != hipSuccess) return hip_fail(e, "learned-zoom network launch");
+  // zoomed gates: K bins around the proposed centre; the others: full spectra
+  st = zoom_impl(z->zoom, samples, tx_code, tx_per_pulse, n_pulses, z->bin_start, z->zoom_list,
+                 z->counts, z->window_spectra, 0, stream);
+  if (st != ISPL_OK) return st;
+  st = integrate_impl(z->fine, samples, tx_code, tx_per_pulse, n_pulses, z->fallback_list,
+                      z->counts + 1, z->full_spectra, 0, stream);
+  if (st != ISPL_OK) return st;
+  e = ispl::launch_window_peak(z->window_spectra, G, z->window_bins, c.fft_len, z->bin_start,
+                               z->zoom_list, z->counts, peak_bin, peak_power, s);
+  if (e == hipSuccess)
+    e = ispl::launch_peak(z->full_spectra, G, c.fft_len, 0, c.fft_len, peak_bin, peak_power,
+                          z->fallback_list, z->counts + 1, s);
+  if (e != hipSuccess) return hip_fail(e, "learned-zoom peak launch");
+  return ok();
+}
+
+ispl_status ispl_lzoom_view(const ispl_lzoom* z, ispl_lzoom_buffers* out) {
+  if (!z || !out) return fail(ISPL_ERR_INVALID_ARG, "NULL argument");
+  out->n_gates = z->n_gates;
+  out->window_bins = z->window_bins;
+  out->fine_len = z->fine->cfg.fft_len;
+  out->coarse_spectra = z->coarse_spectra;
+  out->logits = z->logits;
+  out->bin_start = z->bin_start;
+  out->confidence = z->confidence;
+  out->zoom_list = z->zoom_list;
+  out->fallback_list = z->fallback_list;
+  out->counts = z->counts;
+  out->window_spectra = z->window_spectra;
+  out->full_spectra = z->full_spectra;
   return ok();
 }
 

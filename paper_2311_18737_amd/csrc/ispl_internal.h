@@ -34,6 +34,8 @@ struct FusedArgs {
   int32_t accumulate;      // only read when chunks == 1
   int32_t sample_type;     // 0 c64, 1 ci16
   int32_t waves_per_block; // RW in {1, 2, 4, 8, 16} (16 when M = 16 SUB)
+  const int32_t* gate_list;  // optional: work on gate_list[i], i < *gate_count, only
+  const int32_t* gate_count; // device int32, read by the kernels
 };
 
 // Static LDS bytes of one fused workgroup with `rw` waves and sub-transform M.
@@ -42,10 +44,15 @@ int fused_lds_bytes(int rw, int sub_len);
 hipError_t launch_fused(const FusedArgs& a, hipStream_t stream);
 
 // S[g][k] = (accumulate ? S[g][k] : 0) + sum_{c < C} partial[c][g][k], c ascending.
+// spectra (+)= sum over chunks of partial; with a list, only the rows of the
+// listed gates (list[i], i < *count) are touched.
 hipError_t launch_reduce_chunks(const float* partial, float* spectra, int64_t elems,
-                                int32_t chunks, int32_t accumulate, hipStream_t stream);
+                                int32_t chunks, int32_t accumulate, int32_t n_fft,
+                                const int32_t* list, const int32_t* count, hipStream_t stream);
 
 hipError_t launch_fill_zero(float* dst, int64_t elems, hipStream_t stream);
+hipError_t launch_fill_zero_rows(float* dst, int32_t n_gates, int32_t n_fft, const int32_t* list,
+                                 const int32_t* count, hipStream_t stream);
 
 // Zoom DFT of a K-bin window per gate on the matrix cores.
 struct ZoomArgs {
@@ -69,6 +76,8 @@ struct ZoomArgs {
   int32_t accumulate;
   int32_t sample_type;
   int32_t precision;        // 0: BF16 x3, 1: FP16 x3
+  const int32_t* gate_list; // optional: only gates gate_list[i], i < *gate_count
+  const int32_t* gate_count;
 };
 
 hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream);
@@ -104,6 +113,17 @@ hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int
 
 hipError_t launch_peak(const float* spectra, int32_t n_gates, int32_t n_fft, int32_t bin_lo,
                        int32_t bin_hi, int32_t* peak_bin, float* peak_power,
-                       hipStream_t stream);
+                       const int32_t* list, const int32_t* count, hipStream_t stream);
+
+// Learned-zoom decision kernels.
+hipError_t launch_select_windows(const float* logits, int32_t n_gates, int32_t fine_len,
+                                 int32_t window_bins, float threshold, int32_t* bin_start,
+                                 float* confidence, int32_t* flag, hipStream_t s);
+hipError_t launch_compact_lists(const int32_t* flag, int32_t n_gates, int32_t* zoom_list,
+                                int32_t* fallback_list, int32_t* counts, hipStream_t s);
+hipError_t launch_window_peak(const float* spectra, int32_t n_gates, int32_t window_bins,
+                              int32_t fine_len, const int32_t* bin_start, const int32_t* list,
+                              const int32_t* count, int32_t* peak_bin, float* peak_power,
+                              hipStream_t s);
 
 }  // namespace ispl

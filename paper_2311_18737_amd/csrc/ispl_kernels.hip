@@ -294,6 +294,22 @@ __device__ __forceinline__ int xcd_block_id() {
   return xcd < extra ? xcd * (per + 1) + slot : extra * (per + 1) + (xcd - extra) * per + slot;
 }
 
+// Gate of work slot `slot`: the slot itself, or the slot-th entry of a gate
+// list.  Returns -1 for slots past the list's device-side count and for
+// entries outside [0, n_gates), whose workgroups then do nothing.
+__device__ __forceinline__ int slot_gate(const FusedArgs& a, int slot) {
+  if (!a.gate_list) return slot;
+  if (slot >= *a.gate_count) return -1;
+  const int g = a.gate_list[slot];
+  return (g >= 0 && g < a.n_gates) ? g : -1;
+}
+
+// Listed launches keep the hardware order, which deals the active (leading)
+// slots round-robin over all XCDs; full launches use the XCD-contiguous order.
+__device__ __forceinline__ int work_id(const FusedArgs& a) {
+  return a.gate_list ? static_cast<int>(blockIdx.x) : xcd_block_id();
+}
+
 // Output row of gate g (chunk c when the pulses are split).
 __device__ __forceinline__ float* out_row(const FusedArgs& a, int g, int c) {
   return a.out + (a.chunks == 1 ? static_cast<int64_t>(g) * a.n_fft
@@ -318,11 +334,12 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int R = 1 << a.log2_r;
   const int zgroups = R / RW;
-  int bid = xcd_block_id();
+  int bid = work_id(a);
   const int c = bid % a.chunks;
   bid /= a.chunks;
   const int zg = bid % zgroups;
-  const int g = bid / zgroups;
+  const int g = slot_gate(a, bid / zgroups);
+  if (g < 0) return;  // uniform over the workgroup, before any barrier
   const int k1 = zg * RW + wave;
   const int L = a.code_len;
   const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
@@ -409,11 +426,12 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int R = 1 << a.log2_r;  // N / 16384
-  int bid = xcd_block_id();
+  int bid = work_id(a);
   const int c = bid % a.chunks;
   bid /= a.chunks;
   const int k1 = bid % R;
-  const int g = bid / R;
+  const int g = slot_gate(a, bid / R);
+  if (g < 0) return;  // uniform over the workgroup, before any barrier
   const int N = a.n_fft;
   const int L = a.code_len;
   const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
@@ -476,15 +494,27 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
   }
 }
 
+// S = sum over chunks of the partial spectra (fixed order), for every gate or
+// for the listed gates only (rows of the other gates are left untouched).
 __global__ void __launch_bounds__(256)
 reduce_chunks(const float* __restrict__ partial, float* __restrict__ spectra, int64_t elems,
-              int32_t chunks, int32_t accumulate) {
+              int32_t chunks, int32_t accumulate, int32_t n_fft, const int32_t* __restrict__ list,
+              const int32_t* __restrict__ count) {
+  const int64_t n_gates = elems / n_fft;
+  int64_t active = elems;
+  if (list) active = static_cast<int64_t>(min(max(*count, 0), static_cast<int32_t>(n_gates))) * n_fft;
   const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < elems;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < active;
        i += step) {
-    float s = accumulate ? spectra[i] : 0.f;
-    for (int c = 0; c < chunks; ++c) s += partial[static_cast<int64_t>(c) * elems + i];
-    spectra[i] = s;
+    int64_t j = i;
+    if (list) {
+      const int g = list[i / n_fft];
+      if (g < 0 || g >= n_gates) continue;
+      j = static_cast<int64_t>(g) * n_fft + i % n_fft;
+    }
+    float s = accumulate ? spectra[j] : 0.f;
+    for (int c = 0; c < chunks; ++c) s += partial[static_cast<int64_t>(c) * elems + j];
+    spectra[j] = s;
   }
 }
 
@@ -495,15 +525,34 @@ __global__ void __launch_bounds__(256) fill_zero(float* __restrict__ dst, int64_
     dst[i] = 0.f;
 }
 
+// Zero the rows of the listed gates of a [n_gates][n_fft] array.
+__global__ void __launch_bounds__(256)
+fill_zero_rows(float* __restrict__ dst, int32_t n_gates, int32_t n_fft,
+               const int32_t* __restrict__ list, const int32_t* __restrict__ count) {
+  const int64_t active = static_cast<int64_t>(min(max(*count, 0), n_gates)) * n_fft;
+  const int64_t step = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < active;
+       i += step) {
+    const int g = list[i / n_fft];
+    if (g >= 0 && g < n_gates) dst[static_cast<int64_t>(g) * n_fft + i % n_fft] = 0.f;
+  }
+}
+
 __device__ __forceinline__ bool peak_better(float v, int k, float bv, int bk) {
   return v > bv || (v == bv && k < bk);
 }
 
-// One workgroup per gate: (value, -bin) maximum over the band.
+// One workgroup per gate (per listed gate): (value, -bin) maximum over the band.
 __global__ void __launch_bounds__(256)
-peak_pick(const float* __restrict__ spectra, int32_t n_fft, int32_t lo, int32_t hi,
-          int32_t* __restrict__ peak_bin, float* __restrict__ peak_power) {
-  const int g = blockIdx.x;
+peak_pick(const float* __restrict__ spectra, int32_t n_gates, int32_t n_fft, int32_t lo,
+          int32_t hi, int32_t* __restrict__ peak_bin, float* __restrict__ peak_power,
+          const int32_t* __restrict__ list, const int32_t* __restrict__ count) {
+  int g = blockIdx.x;
+  if (list) {
+    if (g >= *count) return;
+    g = list[g];
+    if (g < 0 || g >= n_gates) return;
+  }
   const float* row = spectra + static_cast<int64_t>(g) * n_fft;
   const int len = lo < hi ? hi - lo : (n_fft - lo) + hi;
   float bv = -INFINITY;
@@ -598,9 +647,10 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t stream) {
 }
 
 hipError_t launch_reduce_chunks(const float* partial, float* spectra, int64_t elems,
-                                int32_t chunks, int32_t accumulate, hipStream_t stream) {
+                                int32_t chunks, int32_t accumulate, int32_t n_fft,
+                                const int32_t* list, const int32_t* count, hipStream_t stream) {
   hipLaunchKernelGGL(reduce_chunks, dim3(grid_for(elems)), dim3(256), 0, stream, partial,
-                     spectra, elems, chunks, accumulate);
+                     spectra, elems, chunks, accumulate, n_fft, list, count);
   return hipGetLastError();
 }
 
@@ -609,11 +659,18 @@ hipError_t launch_fill_zero(float* dst, int64_t elems, hipStream_t stream) {
   return hipGetLastError();
 }
 
+hipError_t launch_fill_zero_rows(float* dst, int32_t n_gates, int32_t n_fft, const int32_t* list,
+                                 const int32_t* count, hipStream_t stream) {
+  hipLaunchKernelGGL(fill_zero_rows, dim3(grid_for(static_cast<int64_t>(n_gates) * n_fft)),
+                     dim3(256), 0, stream, dst, n_gates, n_fft, list, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_peak(const float* spectra, int32_t n_gates, int32_t n_fft, int32_t bin_lo,
                        int32_t bin_hi, int32_t* peak_bin, float* peak_power,
-                       hipStream_t stream) {
+                       const int32_t* list, const int32_t* count, hipStream_t stream) {
   hipLaunchKernelGGL(peak_pick, dim3(static_cast<unsigned>(n_gates)), dim3(256), 0, stream,
-                     spectra, n_fft, bin_lo, bin_hi, peak_bin, peak_power);
+                     spectra, n_gates, n_fft, bin_lo, bin_hi, peak_bin, peak_power, list, count);
   return hipGetLastError();
 }
 

@@ -105,8 +105,13 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int btiles = a.n_bins / 128;
-  const int g = blockIdx.x / btiles;
+  int g = blockIdx.x / btiles;
   const int bt = blockIdx.x % btiles;
+  if (a.gate_list) {  // uniform over the workgroup, before any barrier
+    if (g >= *a.gate_count) return;
+    g = a.gate_list[g];
+    if (g < 0 || g >= a.n_gates) return;
+  }
   const int L = a.code_len, N = a.n_fft, P = a.n_pulses;
   const int nchunks = a.code_pad / ZCHUNK;
   const int k0 = ((a.bin_start[g] % N) + N) % N;
@@ -182,7 +187,9 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
             const float2 x = load_sample<ST>(a.samples, rowp + n);
             const float2 c = txp[n];
             const float2 d = make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
-            const float2 w = tw[(static_cast<int64_t>(k0) * n) % N];
+            // N is a power of two, so k0 n mod N survives the 32-bit wrap
+            const float2 w = tw[(static_cast<uint32_t>(k0) * static_cast<uint32_t>(n)) &
+                                static_cast<uint32_t>(N - 1)];
             y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * scale, fmaf(d.x, w.y, d.y * w.x) * scale);
           }
           uint32_t rh, rl, ih, il;

@@ -126,6 +126,24 @@ def test_null_context_and_null_pointers(ispl_lib):
     assert ispl_lib.ispl_create(None, None) == 1
     h = ctypes.c_void_p()
     assert ispl_lib.ispl_create(None, ctypes.byref(h)) == 1
+    # gate-list variants, window decision and learned zoom
+    assert ispl_lib.ispl_integrate_spectra_gates(None, vp(16), vp(16), 1, 1, vp(16), vp(16),
+                                                 vp(16), 0, None) == 1
+    assert ispl_lib.ispl_find_plasma_line_gates(None, vp(16), 0, 16, vp(16), vp(16), vp(16),
+                                                None, None) == 1
+    assert ispl_lib.ispl_zoom_spectra_gates(None, vp(16), vp(16), 1, 1, vp(16), vp(16), vp(16),
+                                            vp(16), 0, None) == 1
+    assert ispl_lib.ispl_zoom_find_peaks(None, vp(16), vp(16), vp(16), vp(16), vp(16), None,
+                                         None) == 1
+    assert ispl_lib.ispl_net_select(None, vp(16), 4, 16384, 256, 0.9, vp(16), None, vp(16),
+                                    vp(16), vp(16), vp(16), None) == 1
+    lz = ctypes.c_void_p(99)
+    assert ispl_lib.ispl_lzoom_create(ctypes.byref(cfg()), None, 256, 1, 0.9,
+                                      ctypes.byref(lz)) == 1 and lz.value is None
+    assert ispl_lib.ispl_lzoom_create(ctypes.byref(cfg()), vp(16), 256, 1, 0.9, None) == 1
+    assert ispl_lib.ispl_lzoom_peaks(None, vp(16), vp(16), 1, 1, vp(16), None, None) == 1
+    assert ispl_lib.ispl_lzoom_view(None, None) == 1
+    ispl_lib.ispl_lzoom_destroy(None)
 
 
 def test_create_without_gpu_reports_device_error(ispl_lib):
