@@ -251,9 +251,44 @@ struct ispl_zoom {
   int32_t n_bins;
   int32_t precision;
   int32_t code_pad;
+  int32_t chunks_max;
   void* a_hi;
   void* a_lo;
+  float* partial;    // [chunks_max][G][K] when chunks_max > 1
+  int32_t* col_exp;  // [max_pulses] (FP16 only)
 };
+
+namespace {
+
+struct ZoomPlan {
+  int rt, ct, chunks;
+};
+
+// Bins per workgroup: 256 when K allows it (each staged sample feeds twice the
+// matrix work), else 128.  Pulse chunks until there are two workgroups per
+// compute unit, but at least 24 pulses per chunk; column tiles to fit a chunk
+// (at most 2 with 256 bins: 128 accumulator registers would spill).
+ZoomPlan zoom_plan(int32_t n_gates, int32_t n_bins, int32_t n_pulses) {
+  ZoomPlan z{};
+  z.rt = n_bins % 256 == 0 ? 2 : 1;
+  const int64_t base = static_cast<int64_t>(n_gates) * (n_bins / (128 * z.rt));
+  int64_t chunks = base < 2 * kComputeUnits ? (2 * kComputeUnits + base - 1) / base : 1;
+  const int64_t by_pulses = n_pulses / 24 > 1 ? n_pulses / 24 : 1;
+  if (chunks > by_pulses) chunks = by_pulses;
+  z.chunks = static_cast<int>(chunks);
+  const int64_t per = (n_pulses + chunks - 1) / chunks;
+  z.ct = per <= 32 ? 1 : (per <= 64 ? 2 : 4);
+  if (z.rt == 2 && z.ct > 2) z.ct = 2;  // 2 x 4 accumulator tiles would spill
+  return z;
+}
+
+}  // namespace
+
+static void zoom_free(ispl_zoom* z) {
+  void* bufs[] = {z->a_hi, z->a_lo, z->partial, z->col_exp};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+}
 
 extern "C" {
 
@@ -473,19 +508,24 @@ ispl_status ispl_zoom_create(ispl_ctx* ctx, int32_t n_bins, int32_t precision,
   z->n_bins = n_bins;
   z->precision = precision;
   z->code_pad = code_pad;
+  z->chunks_max = zoom_plan(c.n_gates, n_bins, c.max_pulses).chunks;
   const size_t half = hi.size() * sizeof(uint16_t);
   hipError_t e = hipMalloc(&z->a_hi, half);
   if (e == hipSuccess) e = hipMalloc(&z->a_lo, half);
+  if (e == hipSuccess && z->chunks_max > 1)
+    e = hipMalloc(&z->partial, sizeof(float) * static_cast<size_t>(z->chunks_max) * c.n_gates *
+                                   static_cast<size_t>(n_bins));
+  if (e == hipSuccess && precision == ISPL_ZOOM_FP16X3)
+    e = hipMalloc(&z->col_exp, sizeof(int32_t) * static_cast<size_t>(c.max_pulses));
   if (e != hipSuccess) {
-    if (z->a_hi) (void)hipFree(z->a_hi);
+    zoom_free(z);
     delete z;
     return fail(ISPL_ERR_OUT_OF_MEMORY, "zoom table: %s", hipGetErrorString(e));
   }
   e = hipMemcpy(z->a_hi, hi.data(), half, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(z->a_lo, lo.data(), half, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    (void)hipFree(z->a_hi);
-    (void)hipFree(z->a_lo);
+    zoom_free(z);
     delete z;
     return hip_fail(e, "zoom table upload");
   }
@@ -498,8 +538,7 @@ void ispl_zoom_destroy(ispl_zoom* z) {
   {
     DeviceGuard guard(z->ctx->cfg.device);
     (void)hipDeviceSynchronize();
-    if (z->a_hi) (void)hipFree(z->a_hi);
-    if (z->a_lo) (void)hipFree(z->a_lo);
+    zoom_free(z);
   }
   delete z;
 }
@@ -559,8 +598,25 @@ static ispl_status zoom_impl(ispl_zoom* z, const void* samples, const float* tx_
   a.precision = z->precision;
   a.gate_list = gate_list;
   a.gate_count = gate_count;
-  const hipError_t e = ispl::launch_zoom(a, s);
+  const ZoomPlan zp = zoom_plan(c.n_gates, z->n_bins, n_pulses);
+  if (zp.chunks > z->chunks_max)
+    return fail(ISPL_ERR_INVALID_ARG, "internal: zoom plan needs %d chunks > %d", zp.chunks,
+                z->chunks_max);
+  a.chunks = zp.chunks;
+  a.row_tiles = zp.rt;
+  a.col_tiles = zp.ct;
+  a.partial = z->partial;
+  a.col_exp = z->col_exp;
+  a.row_lo = c.first_gate;
+  a.row_hi = static_cast<int64_t>(c.first_gate) + static_cast<int64_t>(c.n_gates - 1) * c.gate_step +
+             c.code_len;
+  hipError_t e = ispl::launch_zoom(a, s);
   if (e != hipSuccess) return hip_fail(e, "zoom launch");
+  if (zp.chunks > 1) {
+    e = ispl::launch_reduce_chunks(z->partial, spectra, static_cast<int64_t>(c.n_gates) * z->n_bins,
+                                   zp.chunks, accumulate, z->n_bins, gate_list, gate_count, s);
+    if (e != hipSuccess) return hip_fail(e, "zoom chunk reduce launch");
+  }
   return ok();
 }
 

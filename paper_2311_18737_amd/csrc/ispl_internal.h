@@ -63,7 +63,10 @@ struct ZoomArgs {
   const void* a_lo;         // low halves
   const int32_t* bin_start; // [G] first bin of each gate's window (taken mod N)
   float* out;               // [G][K]
+  float* partial;           // [chunks][G][K] when chunks > 1
+  int32_t* col_exp;         // [P] per-pulse FP16 exponents (written by the launch)
   int64_t stride;
+  int64_t row_lo, row_hi;   // samples of a pulse row that some gate reads
   int32_t n_fft;            // N
   int32_t code_len;         // L
   int32_t code_pad;         // L rounded up to 64
@@ -71,11 +74,14 @@ struct ZoomArgs {
   int32_t gate_step;
   int32_t first_gate;
   int32_t n_pulses;
-  int32_t n_bins;           // K, a multiple of 128
+  int32_t n_bins;           // K, a multiple of 128 RT
   int32_t tx_per_pulse;
-  int32_t accumulate;
+  int32_t accumulate;       // read when chunks == 1
   int32_t sample_type;
   int32_t precision;        // 0: BF16 x3, 1: FP16 x3
+  int32_t chunks;           // pulse chunks (workgroups per gate and bin tile)
+  int32_t row_tiles;        // RT: 1 or 2 (128 or 256 bins per workgroup)
+  int32_t col_tiles;        // CT: 1, 2 or 4 (32, 64 or 128 pulses per block)
   const int32_t* gate_list; // optional: only gates gate_list[i], i < *gate_count
   const int32_t* gate_count;
 };

@@ -13,17 +13,20 @@
 // Precision: both operands are split into a high and a low 16-bit part
 // (BF16 or FP16) and D = A_hi B_hi + A_hi B_lo + A_lo B_hi accumulates in
 // FP32; the dropped A_lo B_lo term and the split residuals are about 2^-16
-// (BF16) or 2^-22 (FP16) of each product.  FP16 columns are scaled by a power
-// of two so their largest sample sits near 2^14 (no overflow, low parts stay
-// normal) and the scale is removed exactly before the pulse sum.  Decode,
+// (BF16) or 2^-22 (FP16) of each product.  FP16 columns (pulses) are scaled by a
+// power of two that puts the largest decoded sample of the pulse below 2^14
+// (no overflow; low parts stay normal) and the scale is removed exactly
+// before the pulse sum.  Decode,
 // shift and pulse integration run in FP32.
 //
-// Tiling: a workgroup of 8 waves owns one gate and 128 bins (16 per wave, a
-// 32-row MFMA tile each) and sweeps the pulses in blocks of 128 columns (four
-// 32x32 tiles per wave).  The decoded, shifted and split samples of a block
-// are built once per 64-sample chunk in LDS in the MFMA B-operand layout; the
-// A operand (DFT matrix, split) streams from a table laid out in the
-// A-operand order, 16 bytes per lane per step.
+// Tiling: a workgroup of 8 waves owns one gate, 128 or 256 bins (one or two
+// 32-row MFMA tiles per wave) and a chunk of the pulses, which it sweeps in
+// blocks of 32, 64 or 128 columns (32x32 tiles).  The decoded, shifted and
+// split samples of a block are built per 64-sample chunk in LDS in the MFMA
+// B-operand layout, double-buffered so that building overlaps the matrix
+// work; the A operand (DFT matrix, split) streams from a table laid out in
+// the A-operand order, 16 bytes per lane per k-step, one k-step ahead.  Pulse
+// chunks of one gate write partial windows that a fixed-order pass sums.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -39,7 +42,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int ZW = 8;              // waves per workgroup
 constexpr int ZT = 64 * ZW;        // threads
-constexpr int ZCOLS = 128;         // pulses per block (four 32-column tiles)
 constexpr int ZCHUNK = 64;         // samples per B chunk (8 MFMA k-steps of 16 rows)
 constexpr int ZKS = 2 * ZCHUNK / 16;
 
@@ -94,187 +96,301 @@ __device__ __forceinline__ float2 load_sample(const void* base, int64_t i) {
   }
 }
 
-template <int PREC, int ST>
+// Builds one 64-sample chunk of the B operand for this thread's column:
+// groups qg = q0 + NQ i (4 samples each), decoded, shifted to the window,
+// scaled and split into high and low halves, stored in the MFMA layout
+// (k-step qg / 2, lane half qg % 2).
+template <int PREC, int ST, int CT>
+__device__ __forceinline__ void build_chunk(const ZoomArgs& a, Frag (*bh)[ZKS][64],
+                                            Frag (*bl)[ZKS][64], int ch, int pc, int q0,
+                                            bool live, int64_t rowp, const float2* txp,
+                                            uint32_t k0, float scale) {
+  constexpr int NQ = ZT / (32 * CT);
+  const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
+  const uint32_t nmask = static_cast<uint32_t>(a.n_fft - 1);
+#pragma unroll
+  for (int i = 0; i < CT; ++i) {
+    const int qg = q0 + NQ * i;
+    Frag fh, fl;
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int n = ch * ZCHUNK + 4 * qg + s2;
+      float2 y = make_float2(0.f, 0.f);
+      if (live && n < a.code_len) {
+        const float2 x = load_sample<ST>(a.samples, rowp + n);
+        const float2 c = txp[n];
+        const float2 d = make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
+        // N is a power of two, so k0 n mod N survives the 32-bit wrap
+        const float2 w = tw[(k0 * static_cast<uint32_t>(n)) & nmask];
+        y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * scale, fmaf(d.x, w.y, d.y * w.x) * scale);
+      }
+      uint32_t rh, rl, ih, il;
+      split2<PREC>(y.x, rh, rl);
+      split2<PREC>(y.y, ih, il);
+      fh.w[s2] = rh | (ih << 16);
+      fl.w[s2] = rl | (il << 16);
+    }
+    const int ks = qg >> 1, ln = (pc & 31) + 32 * (qg & 1), ct = pc >> 5;
+    bh[ct][ks][ln] = fh;
+    bl[ct][ks][ln] = fl;
+  }
+}
+
+// RT: 32-row MFMA tiles per wave (16 bins each); CT: 32-pulse column tiles per
+// pulse block.  A workgroup owns one gate, 128 RT bins and one chunk of the
+// pulses.  The B chunks are double-buffered in LDS (the next chunk is built
+// while the current one feeds the matrix cores, one barrier per chunk) and
+// the A fragments of the next k-step are loaded while the current ones are
+// multiplied.
+template <int PREC, int ST, int RT, int CT>
 __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
-  __shared__ Frag bh[4][ZKS][64];  // B operand, high parts: [column tile][k-step][lane]
-  __shared__ Frag bl[4][ZKS][64];  // low parts
-  __shared__ int col_exp[ZCOLS];
-  __shared__ float col_max[4][ZCOLS];
+  constexpr int NCOL = 32 * CT;
+  __shared__ Frag bh[2][CT][ZKS][64];  // B operand, high parts: [buffer][tile][k-step][lane]
+  __shared__ Frag bl[2][CT][ZKS][64];  // low parts
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int btiles = a.n_bins / 128;
-  int g = blockIdx.x / btiles;
-  const int bt = blockIdx.x % btiles;
+  const int btiles = a.n_bins / (128 * RT);
+  int bid = blockIdx.x;
+  const int chunk = bid % a.chunks;
+  bid /= a.chunks;
+  const int bt = bid % btiles;
+  int g = bid / btiles;
   if (a.gate_list) {  // uniform over the workgroup, before any barrier
     if (g >= *a.gate_count) return;
     g = a.gate_list[g];
     if (g < 0 || g >= a.n_gates) return;
   }
-  const int L = a.code_len, N = a.n_fft, P = a.n_pulses;
+  const int L = a.code_len, N = a.n_fft;
+  const int p0 = static_cast<int>((static_cast<int64_t>(chunk) * a.n_pulses) / a.chunks);
+  const int p1 = static_cast<int>((static_cast<int64_t>(chunk + 1) * a.n_pulses) / a.chunks);
   const int nchunks = a.code_pad / ZCHUNK;
-  const int k0 = ((a.bin_start[g] % N) + N) % N;
-  const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
+  const int n_ks = nchunks * ZKS;
+  const uint32_t k0 = static_cast<uint32_t>(((a.bin_start[g] % N) + N) % N);
   const float2* __restrict__ txb = reinterpret_cast<const float2*>(a.tx);
   const int64_t gate_off = static_cast<int64_t>(a.first_gate) + static_cast<int64_t>(g) * a.gate_step;
 
-  // A operand of this wave: row tile rt of the table, k-steps along the code
-  const int rt = bt * ZW + wave;
-  const Frag* __restrict__ ah_t = reinterpret_cast<const Frag*>(a.a_hi) +
-                                  static_cast<int64_t>(rt) * (a.code_pad / 8) * 64;
-  const Frag* __restrict__ al_t = reinterpret_cast<const Frag*>(a.a_lo) +
-                                  static_cast<int64_t>(rt) * (a.code_pad / 8) * 64;
-
-  // per-lane sums of the 8 bins this lane reduces (bins 2 (4 q + s) + h ... see below)
-  float total[8];
+  // A operand of this wave: row tiles (bt ZW + wave) RT + r, k-steps along the code
+  const Frag* __restrict__ ah_t[RT];
+  const Frag* __restrict__ al_t[RT];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) total[i] = 0.f;
+  for (int r = 0; r < RT; ++r) {
+    const int64_t rt = static_cast<int64_t>((bt * ZW + wave) * RT + r);
+    ah_t[r] = reinterpret_cast<const Frag*>(a.a_hi) + rt * n_ks * 64 + lane;
+    al_t[r] = reinterpret_cast<const Frag*>(a.a_lo) + rt * n_ks * 64 + lane;
+  }
 
-  // B-building role: column (pulse) pc of the block, sample groups q, q + 4, ...
-  const int pc = tid % ZCOLS, q0 = tid / ZCOLS;  // q0 in 0..3
+  float total[RT][8];
+#pragma unroll
+  for (int r = 0; r < RT; ++r)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) total[r][i] = 0.f;
 
-  for (int pb = 0; pb < P; pb += ZCOLS) {
+  // B-building role: column pc of the block, group rows q0, q0 + NQ, ...
+  const int pc = tid % NCOL, q0 = tid / NCOL;
+
+  for (int pb = p0; pb < p1; pb += NCOL) {
     const int p = pb + pc;
-    const bool live = p < P;
-    const int64_t rowp = static_cast<int64_t>(live ? p : 0) * a.stride + gate_off;
-    const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(live ? p : 0) * L : 0);
+    const bool live = p < p1;
+    const int64_t rowp = static_cast<int64_t>(live ? p : p0) * a.stride + gate_off;
+    const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(live ? p : p0) * L : 0);
+    const float scale = (PREC == 1 && live) ? ldexpf(1.f, a.col_exp[p]) : 1.f;
 
-    // column scale: 2^e with max |y'| 2^e near 2^14 (FP16), 1 (BF16)
-    if (PREC == 1) {
-      float m = 0.f;
-      if (live)
-        for (int n = q0; n < L; n += 4) {
-          const float2 x = load_sample<ST>(a.samples, rowp + n);
-          const float2 c = txp[n];
-          m = fmaxf(m, (x.x * x.x + x.y * x.y) * (c.x * c.x + c.y * c.y));
-        }
-      col_max[q0][pc] = m;
-      __syncthreads();
-      if (q0 == 0) {
-        const float mm = fmaxf(fmaxf(col_max[0][pc], col_max[1][pc]),
-                               fmaxf(col_max[2][pc], col_max[3][pc]));
-        int e = 0;
-        if (mm > 0.f) {
-          int ex;
-          frexpf(sqrtf(mm), &ex);  // sqrt(mm) < 2^ex
-          e = 14 - ex;
-        }
-        col_exp[pc] = e;
-      }
-      __syncthreads();
+    f32x16 acc[RT][CT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[r][ct][i] = 0.f;
+
+    build_chunk<PREC, ST, CT>(a, bh[0], bl[0], 0, pc, q0, live, rowp, txp, k0, scale);
+    Frag nh[RT], nl[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      nh[r] = ah_t[r][0];
+      nl[r] = al_t[r][0];
     }
-    const float scale = PREC == 1 ? ldexpf(1.f, col_exp[pc]) : 1.f;
-
-    f32x16 acc[4];
-#pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[ct][r] = 0.f;
-
+    __syncthreads();
     for (int ch = 0; ch < nchunks; ++ch) {
-      // build the B chunk: group q covers samples 4 q .. 4 q + 3 of the chunk,
-      // i.e. reduction rows 8 q .. 8 q + 7 = k-step q / 2, lane half q % 2
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int qg = q0 + 4 * i;
-        Frag fh, fl;
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) {
-          const int n = ch * ZCHUNK + 4 * qg + s2;
-          float2 y = make_float2(0.f, 0.f);
-          if (live && n < L) {
-            const float2 x = load_sample<ST>(a.samples, rowp + n);
-            const float2 c = txp[n];
-            const float2 d = make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
-            // N is a power of two, so k0 n mod N survives the 32-bit wrap
-            const float2 w = tw[(static_cast<uint32_t>(k0) * static_cast<uint32_t>(n)) &
-                                static_cast<uint32_t>(N - 1)];
-            y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * scale, fmaf(d.x, w.y, d.y * w.x) * scale);
-          }
-          uint32_t rh, rl, ih, il;
-          split2<PREC>(y.x, rh, rl);
-          split2<PREC>(y.y, ih, il);
-          fh.w[s2] = rh | (ih << 16);
-          fl.w[s2] = rl | (il << 16);
-        }
-        const int ks = qg >> 1, ln = (pc & 31) + 32 * (qg & 1), ct = pc >> 5;
-        bh[ct][ks][ln] = fh;
-        bl[ct][ks][ln] = fl;
-      }
-      __syncthreads();
+      const int b = ch & 1;
+      if (ch + 1 < nchunks)
+        build_chunk<PREC, ST, CT>(a, bh[b ^ 1], bl[b ^ 1], ch + 1, pc, q0, live, rowp, txp, k0,
+                                  scale);
 #pragma unroll
       for (int ks = 0; ks < ZKS; ++ks) {
-        const int64_t ai = static_cast<int64_t>(ch * ZKS + ks) * 64 + lane;
-        const Frag fah = ah_t[ai], fal = al_t[ai];
+        Frag fh[RT], fl[RT];
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-          const Frag fbh = bh[ct][ks][lane], fbl = bl[ct][ks][lane];
-          acc[ct] = mfma<PREC>(fah, fbh, acc[ct]);
-          acc[ct] = mfma<PREC>(fah, fbl, acc[ct]);
-          acc[ct] = mfma<PREC>(fal, fbh, acc[ct]);
+        for (int r = 0; r < RT; ++r) {
+          fh[r] = nh[r];
+          fl[r] = nl[r];
+        }
+        const int nx = ch * ZKS + ks + 1;
+        if (nx < n_ks) {
+#pragma unroll
+          for (int r = 0; r < RT; ++r) {
+            nh[r] = ah_t[r][static_cast<int64_t>(nx) * 64];
+            nl[r] = al_t[r][static_cast<int64_t>(nx) * 64];
+          }
+        }
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) {
+          const Frag fbh = bh[b][ct][ks][lane], fbl = bl[b][ct][ks][lane];
+#pragma unroll
+          for (int r = 0; r < RT; ++r) {
+            acc[r][ct] = mfma<PREC>(fh[r], fbh, acc[r][ct]);
+            acc[r][ct] = mfma<PREC>(fh[r], fbl, acc[r][ct]);
+            acc[r][ct] = mfma<PREC>(fl[r], fbh, acc[r][ct]);
+          }
         }
       }
       __syncthreads();
     }
 
-    // |Z|^2 per (bin, pulse).  D row (r % 4) + 8 (r / 4) + 4 h (h = lane / 32)
-    // is Re (even) or Im (odd) of wave bin row / 2, so registers r, r + 1 with
-    // r % 4 in {0, 2} are one bin: local bin 2 (r / 4)... b = {0,1} + 4 (r / 4) + 2 h.
-    float pw[8];
+    // |Z|^2 per (bin, pulse).  D row (i % 4) + 8 (i / 4) + 4 h (h = lane / 32) is Re
+    // (even) or Im (odd) of tile bin row / 2: registers 4 qa + 2 s and 4 qa + 2 s + 1
+    // are bin s + 4 qa + 2 h of the tile.
 #pragma unroll
-    for (int i = 0; i < 8; ++i) pw[i] = 0.f;
+    for (int r = 0; r < RT; ++r) {
+      float pw[8];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-      const int pcol = pb + 32 * ct + (lane & 31);
-      const float un = PREC == 1 && pcol < P ? ldexpf(1.f, -2 * col_exp[32 * ct + (lane & 31)]) : 1.f;
+      for (int i = 0; i < 8; ++i) pw[i] = 0.f;
+#pragma unroll
+      for (int ct = 0; ct < CT; ++ct) {
+        const int pcol = pb + 32 * ct + (lane & 31);
+        const float un = (PREC == 1 && pcol < p1) ? ldexpf(1.f, -2 * a.col_exp[pcol]) : 1.f;
+#pragma unroll
+        for (int qa = 0; qa < 4; ++qa)
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            const float re = acc[r][ct][4 * qa + 2 * s], im = acc[r][ct][4 * qa + 2 * s + 1];
+            pw[2 * qa + s] += fmaf(re, re, im * im) * un;
+          }
+      }
+      // sum over the 32 pulse columns of each half wave, fixed order
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        float v = pw[i];
+#pragma unroll
+        for (int off = 1; off < 32; off <<= 1) v += __shfl_xor(v, off);
+        total[r][i] += v;
+      }
+    }
+  }
+
+  // lane 0 holds tile bins s + 4 qa (h = 0), lane 32 bins s + 4 qa + 2 (h = 1)
+  if ((lane & 31) == 0) {
+    const int h = lane >> 5;
+    float* row = a.chunks == 1
+                     ? a.out + static_cast<int64_t>(g) * a.n_bins
+                     : a.partial + (static_cast<int64_t>(chunk) * a.n_gates + g) * a.n_bins;
+    const bool add = a.chunks == 1 && a.accumulate;
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      float* out = row + bt * 128 * RT + 16 * (wave * RT + r);
 #pragma unroll
       for (int qa = 0; qa < 4; ++qa)
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
-          const float re = acc[ct][4 * qa + 2 * s], im = acc[ct][4 * qa + 2 * s + 1];
-          pw[2 * qa + s] += fmaf(re, re, im * im) * un;
+          float* dst = out + s + 4 * qa + 2 * h;
+          *dst = add ? *dst + total[r][2 * qa + s] : total[r][2 * qa + s];
         }
     }
-    // sum over the 32 pulse columns of each half wave, fixed order
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      float v = pw[i];
-#pragma unroll
-      for (int off = 1; off < 32; off <<= 1) v += __shfl_xor(v, off);
-      total[i] += v;
-    }
-    __syncthreads();  // column scales are rewritten by the next block
   }
+}
 
-  // lane 0 holds bins b = s + 4 qa (h = 0), lane 32 bins s + 4 qa + 2 (h = 1)
-  if ((lane & 31) == 0) {
-    const int h = lane >> 5;
-    float* out = a.out + static_cast<int64_t>(g) * a.n_bins + bt * 128 + 16 * wave;
-#pragma unroll
-    for (int qa = 0; qa < 4; ++qa)
-#pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        float* dst = out + s + 4 * qa + 2 * h;
-        *dst = a.accumulate ? *dst + total[2 * qa + s] : total[2 * qa + s];
-      }
+// Per-pulse FP16 exponent: 2^e with max|x| max|c| 2^e < 2^14 over the samples
+// every gate of the pulse reads, so no split value overflows and the low
+// halves stay normal down to about 2^-17 of that maximum.
+__global__ void __launch_bounds__(256)
+pulse_exponents(const void* __restrict__ samples, int32_t sample_type, const float* __restrict__ tx,
+                int64_t stride, int64_t lo, int64_t hi, int32_t code_len, int32_t tx_per_pulse,
+                int32_t* __restrict__ exps) {
+  __shared__ float red[2][4];
+  const int p = blockIdx.x;
+  float mx = 0.f, mc = 0.f;
+  const int64_t base = static_cast<int64_t>(p) * stride;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const float2 x = sample_type == 1 ? load_sample<1>(samples, base + i)
+                                      : load_sample<0>(samples, base + i);
+    mx = fmaxf(mx, x.x * x.x + x.y * x.y);
   }
+  const float2* txp = reinterpret_cast<const float2*>(tx) +
+                      (tx_per_pulse ? static_cast<int64_t>(p) * code_len : 0);
+  for (int n = threadIdx.x; n < code_len; n += 256) {
+    const float2 c = txp[n];
+    mc = fmaxf(mc, c.x * c.x + c.y * c.y);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, off));
+    mc = fmaxf(mc, __shfl_xor(mc, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = mx;
+    red[1][threadIdx.x >> 6] = mc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+    mc = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+    int e = 0;
+    const float m = sqrtf(mx) * sqrtf(mc);
+    if (m > 0.f && isfinite(m)) {
+      int ex;
+      frexpf(m, &ex);  // m < 2^ex
+      e = 14 - ex;
+    }
+    exps[p] = max(-60, min(60, e));
+  }
+}
+
+template <int PREC, int ST, int RT>
+hipError_t launch_zoom_rt(const ZoomArgs& a, int ct, hipStream_t stream) {
+  const unsigned blocks =
+      static_cast<unsigned>(a.n_gates) * (a.n_bins / (128 * RT)) * static_cast<unsigned>(a.chunks);
+  switch (ct) {
+    case 1:
+      hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 1>), dim3(blocks), dim3(ZT), 0, stream, a);
+      break;
+    case 2:
+      hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 2>), dim3(blocks), dim3(ZT), 0, stream, a);
+      break;
+    default:
+      if constexpr (RT == 1) {
+        hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 4>), dim3(blocks), dim3(ZT), 0, stream, a);
+      } else {
+        return hipErrorInvalidValue;  // 2 x 4 accumulator tiles would spill
+      }
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <int PREC, int ST>
+hipError_t launch_zoom_st(const ZoomArgs& a, hipStream_t stream) {
+  return a.row_tiles == 2 ? launch_zoom_rt<PREC, ST, 2>(a, a.col_tiles, stream)
+                          : launch_zoom_rt<PREC, ST, 1>(a, a.col_tiles, stream);
 }
 
 template <int PREC>
 hipError_t launch_zoom_t(const ZoomArgs& a, hipStream_t stream) {
-  const unsigned blocks = static_cast<unsigned>(a.n_gates) * (a.n_bins / 128);
-  if (a.sample_type == 1)
-    hipLaunchKernelGGL((zoom_spectra<PREC, 1>), dim3(blocks), dim3(ZT), 0, stream, a);
-  else
-    hipLaunchKernelGGL((zoom_spectra<PREC, 0>), dim3(blocks), dim3(ZT), 0, stream, a);
-  return hipGetLastError();
+  return a.sample_type == 1 ? launch_zoom_st<PREC, 1>(a, stream) : launch_zoom_st<PREC, 0>(a, stream);
 }
 
 }  // namespace
 
 hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream) {
-  return a.precision == 1 ? launch_zoom_t<1>(a, stream) : launch_zoom_t<0>(a, stream);
+  if (a.precision == 1) {
+    hipLaunchKernelGGL(pulse_exponents, dim3(static_cast<unsigned>(a.n_pulses)), dim3(256), 0,
+                       stream, a.samples, a.sample_type, a.tx, a.stride, a.row_lo, a.row_hi,
+                       a.code_len, a.tx_per_pulse, a.col_exp);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_zoom_t<1>(a, stream);
+  }
+  return launch_zoom_t<0>(a, stream);
 }
 
 }  // namespace ispl
