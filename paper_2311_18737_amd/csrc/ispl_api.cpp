@@ -65,6 +65,7 @@ constexpr int kComputeUnits = 256;
 constexpr int kLdsPerCu = 160 * 1024;
 constexpr int kMaxWavesPerCu = 16;
 constexpr int kMaxChunks = 256;
+constexpr int kMinChunkPulses = 8;
 #ifndef ISPL_MAX_WAVES_PER_BLOCK  // build-time tuning knob (1, 2, 4, 8 or 16)
 #define ISPL_MAX_WAVES_PER_BLOCK 16
 #endif
@@ -97,10 +98,12 @@ Plan make_plan(const ispl_config& c, int32_t n_pulses) {
   if (per_cu < 1) per_cu = 1;
   const int64_t slots = int64_t{kComputeUnits} * per_cu;
   const int64_t base = static_cast<int64_t>(c.n_gates) * pl.zgroups;
-  // enough workgroups for two rounds over the chip, but never empty chunks
+  // enough workgroups for two rounds over the chip, but at least kMinChunkPulses
+  // pulses per chunk (a chunk's partial spectrum costs a write and a read)
   int64_t chunks = 1;
   if (base < 2 * slots) chunks = (2 * slots + base - 1) / base;
-  if (chunks > n_pulses) chunks = n_pulses;
+  const int64_t by_pulses = n_pulses / kMinChunkPulses;
+  if (chunks > by_pulses) chunks = by_pulses;
   if (chunks > kMaxChunks) chunks = kMaxChunks;
   const int64_t gn_bytes = static_cast<int64_t>(c.n_gates) * c.fft_len * 4;
   if (chunks > 1 && chunks * gn_bytes > kMaxPartialBytes) chunks = kMaxPartialBytes / gn_bytes;

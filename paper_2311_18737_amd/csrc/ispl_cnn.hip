@@ -318,13 +318,14 @@ hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int
 // Inference on the matrix cores: BF16 weights and activations, FP32
 // accumulation.  One workgroup (4 waves) per gate keeps the whole gate in
 // LDS: the input row, and two [T][32] BF16 activation buffers used in turn.
-// Layers 1 and 4 (one channel in or out) run on the vector ALUs; layers 2 and
-// 3 are GEMMs D[co][t] = sum_{kk,ci} W[co][ci][kk] A[(t + kk - 3) mod T][ci]
-// on v_mfma_f32_32x32x16_bf16 with the reduction index k = 32 kk + ci.
-// Activation rows are 64 bytes (32 channels); the four 16-byte channel groups
-// of row t are stored at group position g ^ ((t >> 1) & 3), which puts the
-// eight 16-byte reads of consecutive rows that one LDS cycle serves on
-// distinct banks.
+// Layers 1-3 are GEMMs D[co][t] = sum_k A[co][k] B[k][t] on
+// v_mfma_f32_32x32x16_bf16: layer 1 with k = tap (7 of 16 used), layers 2 and
+// 3 with k = 32 tap + ci (14 k-steps); each wave holds its A fragments in
+// registers for the whole layer and sweeps eight 32-position tiles.  Layer 4
+// (one output channel) runs on the vector ALUs.  Activation rows are 64 bytes
+// (32 channels); the four 16-byte channel groups of row t are stored at group
+// position g ^ ((t >> 1) & 3), which puts the eight 16-byte accesses of
+// consecutive rows that one LDS cycle serves on distinct banks.
 
 namespace ispl {
 namespace {
@@ -348,14 +349,15 @@ __device__ __forceinline__ int act_idx(int t, int ci) {
   return t * 32 + 8 * ((ci >> 3) ^ ((t >> 1) & 3)) + (ci & 7);
 }
 
-// Weight tables of the matrix-core layers: for layer l in {2, 3}, k-step ks and
-// lane ln, the 8 BF16 values W[co = ln % 32][ci][kk] with k = 16 ks + 8 (ln / 32) + i,
-// kk = k / 32, ci = k % 32.  Also BF16 copies of W1 and W4 and the FP32 biases.
+// Weight tables of the matrix-core layers.  w1[ln]: layer 1's A fragment,
+// W1[co = ln % 32][k = 8 (ln / 32) + i] for k < 7, zero above.  w2, w3 [ks][ln]:
+// the 8 BF16 values W[co = ln % 32][ci][kk] with k = 16 ks + 8 (ln / 32) + i,
+// kk = k / 32, ci = k % 32.  w4: BF16-rounded W4[ci][kk] as floats.  Biases FP32.
 struct NetBf16 {
+  Frag8 w1[64];
   Frag8 w2[14][64];
   Frag8 w3[14][64];
-  uint16_t w1[32 * 7];
-  uint16_t w4[32 * 7];
+  float w4[32 * 7];
   float b1[32], b2[32], b3[32], b4;
 };
 
@@ -366,23 +368,28 @@ __global__ void __launch_bounds__(256) prep_bf16(const float* __restrict__ p, Ne
     const float* W = p + (layer == 0 ? 256 : 7456);
     Frag8 f;
     for (int i = 0; i < 8; i += 2) {
-      uint32_t lo, hi;
-      {
-        const int k = 16 * ks + 8 * (ln / 32) + i, kk = k / 32, ci = k % 32, co = ln % 32;
-        lo = to_bf16(W[(co * 32 + ci) * 7 + kk]);
+      uint32_t half[2];
+      for (int u = 0; u < 2; ++u) {
+        const int k = 16 * ks + 8 * (ln / 32) + i + u, kk = k / 32, ci = k % 32, co = ln % 32;
+        half[u] = to_bf16(W[(co * 32 + ci) * 7 + kk]);
       }
-      {
-        const int k = 16 * ks + 8 * (ln / 32) + i + 1, kk = k / 32, ci = k % 32, co = ln % 32;
-        hi = to_bf16(W[(co * 32 + ci) * 7 + kk]);
-      }
-      f.w[i / 2] = lo | (hi << 16);
+      f.w[i / 2] = half[0] | (half[1] << 16);
     }
     (layer == 0 ? out->w2 : out->w3)[ks][ln] = f;
   }
-  for (int e = tid; e < 224; e += 256) {
-    out->w1[e] = static_cast<uint16_t>(to_bf16(p[e]));
-    out->w4[e] = static_cast<uint16_t>(to_bf16(p[14656 + e]));
+  if (tid < 64) {
+    Frag8 f;
+    for (int i = 0; i < 8; i += 2) {
+      uint32_t half[2];
+      for (int u = 0; u < 2; ++u) {
+        const int k = 8 * (tid / 32) + i + u, co = tid % 32;
+        half[u] = k < 7 ? to_bf16(p[co * 7 + k]) : 0u;
+      }
+      f.w[i / 2] = half[0] | (half[1] << 16);
+    }
+    out->w1[tid] = f;
   }
+  for (int e = tid; e < 224; e += 256) out->w4[e] = from_bf16(to_bf16(p[14656 + e]));
   if (tid < 32) {
     out->b1[tid] = p[224 + tid];
     out->b2[tid] = p[7424 + tid];
@@ -391,10 +398,28 @@ __global__ void __launch_bounds__(256) prep_bf16(const float* __restrict__ p, Ne
   if (tid == 0) out->b4 = p[14880];
 }
 
+// bias + ReLU of one 32 x 32 accumulator tile (D[co][t], co = (r % 4) + 8 (r / 4) + 4 h,
+// t = this lane's column), rounded to BF16 and stored as four 8-byte groups.
+__device__ __forceinline__ void store_tile(const nf32x16& acc, const float* bias, int h, int t,
+                                           uint16_t* dst) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int co = 8 * q + 4 * h;
+    const uint32_t v01 = to_bf16(fmaxf(acc[4 * q + 0] + bias[co + 0], 0.f)) |
+                         (to_bf16(fmaxf(acc[4 * q + 1] + bias[co + 1], 0.f)) << 16);
+    const uint32_t v23 = to_bf16(fmaxf(acc[4 * q + 2] + bias[co + 2], 0.f)) |
+                         (to_bf16(fmaxf(acc[4 * q + 3] + bias[co + 3], 0.f)) << 16);
+    *reinterpret_cast<uint2*>(dst + act_idx(t, co)) = make_uint2(v01, v23);
+  }
+}
+
 __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ src, uint16_t* __restrict__ dst,
                                            const Frag8 (*__restrict__ wt)[64], const float* bias,
                                            int wave, int lane) {
   const int h = lane >> 5, c = lane & 31;
+  Frag8 afr[14];
+#pragma unroll
+  for (int ks = 0; ks < 14; ++ks) afr[ks] = wt[ks][lane];
   for (int tile = 0; tile < 8; ++tile) {
     const int t = 256 * wave + 32 * tile + c;  // this lane's column
     nf32x16 acc;
@@ -405,20 +430,10 @@ __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ src, uin
       const int kk = ks >> 1, ci0 = 16 * (ks & 1) + 8 * h;
       const int row = (t + kk - PAD) & (T - 1);
       const Frag8 bfr = *reinterpret_cast<const Frag8*>(src + act_idx(row, ci0));
-      const Frag8 afr = wt[ks][lane];
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, afr),
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, afr[ks]),
                                                     __builtin_bit_cast(nbf16x8, bfr), acc, 0, 0, 0);
     }
-    // D[co][t]: co = (r % 4) + 8 (r / 4) + 4 h; four consecutive channels per 8 bytes
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int co = 8 * q + 4 * h;
-      uint32_t v01 = to_bf16(fmaxf(acc[4 * q + 0] + bias[co + 0], 0.f)) |
-                     (to_bf16(fmaxf(acc[4 * q + 1] + bias[co + 1], 0.f)) << 16);
-      uint32_t v23 = to_bf16(fmaxf(acc[4 * q + 2] + bias[co + 2], 0.f)) |
-                     (to_bf16(fmaxf(acc[4 * q + 3] + bias[co + 3], 0.f)) << 16);
-      *reinterpret_cast<uint2*>(dst + act_idx(t, co)) = make_uint2(v01, v23);
-    }
+    store_tile(acc, bias, h, t, dst);
   }
 }
 
@@ -430,27 +445,30 @@ __global__ void __launch_bounds__(256) net_forward_bf16(const float* __restrict_
   __shared__ __attribute__((aligned(16))) uint16_t act1[T * 32];
   const int g = blockIdx.x, j = threadIdx.x, lane = j & 63;
   const int wave = __builtin_amdgcn_readfirstlane(j >> 6);
+  const int h = lane >> 5, c = lane & 31;
   reinterpret_cast<float4*>(xs)[j] = reinterpret_cast<const float4*>(x + static_cast<int64_t>(g) * T)[j];
   __syncthreads();
-  // layer 1: positions 4 j .. 4 j + 3, input rounded to BF16
+  // layer 1: one k-step, B[k][t] = bf16(x[t + k - 3]) for k < 7 (lanes h = 1 hold k >= 8: zero)
   {
-    float w[10];
-    window10(xs, j, w);
+    const Frag8 a1 = nw->w1[lane];
+    for (int tile = 0; tile < 8; ++tile) {
+      const int t = 256 * wave + 32 * tile + c;
+      Frag8 bfr;
 #pragma unroll
-    for (int i = 0; i < 10; ++i) w[i] = from_bf16(to_bf16(w[i]));
-    for (int co = 0; co < 32; ++co) {
-      float acc[4];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) acc[m] = nw->b1[co];
-#pragma unroll
-      for (int k = 0; k < TAPS; ++k) {
-        const float wk = from_bf16(nw->w1[co * 7 + k]);
-#pragma unroll
-        for (int m = 0; m < 4; ++m) acc[m] = fmaf(wk, w[m + k], acc[m]);
+      for (int i = 0; i < 8; i += 2) {
+        uint32_t lo = 0, hi = 0;
+        if (h == 0) {
+          lo = to_bf16(xs[(t + i - PAD) & (T - 1)]);
+          if (i + 1 < TAPS) hi = to_bf16(xs[(t + i + 1 - PAD) & (T - 1)]);
+        }
+        bfr.w[i / 2] = lo | (hi << 16);
       }
+      nf32x16 acc;
 #pragma unroll
-      for (int m = 0; m < 4; ++m)
-        act0[act_idx(4 * j + m, co)] = static_cast<uint16_t>(to_bf16(fmaxf(acc[m], 0.f)));
+      for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, a1),
+                                                    __builtin_bit_cast(nbf16x8, bfr), acc, 0, 0, 0);
+      store_tile(acc, nw->b1, h, t, act0);
     }
   }
   __syncthreads();
@@ -458,23 +476,34 @@ __global__ void __launch_bounds__(256) net_forward_bf16(const float* __restrict_
   __syncthreads();
   mfma_layer(act1, act0, nw->w3, nw->b3, wave, lane);
   __syncthreads();
-  // layer 4
+  // layer 4: thread j computes positions t = j + 256 m (consecutive lanes read
+  // consecutive rows: conflict-free 16-byte LDS reads)
+  float* out = logits + static_cast<int64_t>(g) * T;
   float acc[4];
 #pragma unroll
   for (int m = 0; m < 4; ++m) acc[m] = nw->b4;
-  for (int ci = 0; ci < 32; ++ci) {
-    float w[10];
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
 #pragma unroll
-    for (int i = 0; i < 10; ++i) w[i] = from_bf16(act0[act_idx((4 * j - 3 + i) & (T - 1), ci)]);
+    for (int kk = 0; kk < TAPS; ++kk) {
+      float w[8];
 #pragma unroll
-    for (int k = 0; k < TAPS; ++k) {
-      const float wk = from_bf16(nw->w4[ci * 7 + k]);
+      for (int i = 0; i < 8; ++i) w[i] = nw->w4[(8 * q + i) * TAPS + kk];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) acc[m] = fmaf(wk, w[m + k], acc[m]);
+      for (int m = 0; m < 4; ++m) {
+        const int row = (j + 256 * m + kk - PAD) & (T - 1);
+        const uint4 v = *reinterpret_cast<const uint4*>(act0 + act_idx(row, 8 * q));
+        const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          acc[m] = fmaf(w[2 * i], __uint_as_float(u[i] << 16), acc[m]);
+          acc[m] = fmaf(w[2 * i + 1], __uint_as_float(u[i] & 0xffff0000u), acc[m]);
+        }
+      }
     }
   }
-  *reinterpret_cast<float4*>(logits + static_cast<int64_t>(g) * T + 4 * j) =
-      make_float4(acc[0], acc[1], acc[2], acc[3]);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) out[j + 256 * m] = acc[m];
 }
 
 }  // namespace

@@ -102,8 +102,9 @@ def test_plans_of_named_workloads(ispl_lib):
     small = cfg(code_len=256, fft_len=1024, n_gates=64, pulse_stride=1856, sample_type=0,
                 max_pulses=100)
     st, ch, w, b = plan(ispl_lib, small, 100)
-    assert st == 0 and w == 1 and 1 < ch <= 100 and b == 64 * ch
-    assert plan(ispl_lib, small, 3)[1] == 3          # never more chunks than pulses
+    assert st == 0 and w == 1 and 1 < ch <= 100 // 8 and b == 64 * ch  # >= 8 pulses a chunk
+    assert plan(ispl_lib, small, 3)[1] == 1          # too few pulses to split
+    assert plan(ispl_lib, small, 16)[1] == 2
     assert plan(ispl_lib, small, 0)[1:] == (0, 1, 0)  # empty input launches nothing
     assert plan(ispl_lib, small, 101)[0] == _lib.ISPL_ERR_INVALID_ARG
     assert plan(ispl_lib, small, -1)[0] == _lib.ISPL_ERR_INVALID_ARG
