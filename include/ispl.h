@@ -256,7 +256,9 @@ ispl_status ispl_net_train_step(ispl_net* net, const float* features, const floa
  * [2]) their numbers.  confidence may be NULL.  fine_len: a power of two
  * >= 1024; 2 S < window_bins <= fine_len; 0 < threshold <= 1.  This rule is
  * the project's (the paper computes every gate at full resolution); all
- * arithmetic is FP32.
+ * arithmetic is FP32.  Decision and compaction run in one launch whose last
+ * workgroup compacts, using a completion counter owned by `net`: calls on one
+ * net must not overlap on different streams.
  */
 ispl_status ispl_net_select(ispl_net* net, const float* logits, int32_t n_gates,
                             int32_t fine_len, int32_t window_bins, float threshold,
@@ -281,8 +283,11 @@ ispl_status ispl_net_select(ispl_net* net, const float* logits, int32_t n_gates,
  * window_bins <= fft_len; zoom_precision an ispl_zoom_precision; threshold
  * in (0, 1].  `net` stays owned by the caller, must outlive the object and
  * be on cfg->device; its current parameters are used at every call.  The
- * object owns two contexts, a zoom table and [n_gates] x (3 * 1024 +
- * window_bins + fft_len) floats of buffers.  Not thread-safe.
+ * object owns two contexts, a zoom table and [n_gates] x (2 * 1024 +
+ * window_bins + fft_len) floats of buffers.  Not thread-safe, and calls on
+ * one object must not overlap on different streams (it owns the scratch and
+ * the decision's completion counter).  Capturable in a HIP graph (it neither
+ * allocates nor synchronises).
  */
 typedef struct ispl_lzoom ispl_lzoom;
 

@@ -672,6 +672,7 @@ struct ispl_net {
   float* adam_m;
   float* adam_v;
   float* bf16_weights;  // matrix-core copies, rebuilt when the parameters change
+  int32_t* select_done; // completion counter of the window decision (zero between calls)
   bool bf16_stale;
 };
 
@@ -680,7 +681,7 @@ namespace {
 void net_free(ispl_net* n) {
   void* bufs[] = {n->w.params, n->w.a1, n->w.a2, n->w.a3, n->w.logits, n->w.dz4, n->w.dzA,
                   n->w.dzB, n->w.part, n->w.loss, n->grad, n->adam_m, n->adam_v,
-                  n->bf16_weights};
+                  n->bf16_weights, n->select_done};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -709,7 +710,8 @@ ispl_status ispl_net_create(int32_t device, int32_t max_batch, ispl_net** out) {
       {&n->w.params, P}, {&n->w.a1, B * 32 * T}, {&n->w.a2, B * 32 * T}, {&n->w.a3, B * 32 * T},
       {&n->w.logits, B * T}, {&n->w.dz4, B * T}, {&n->w.dzA, B * 32 * T}, {&n->w.dzB, B * 32 * T},
       {&n->w.part, B * P}, {&n->w.loss, B}, {&n->grad, P}, {&n->adam_m, P}, {&n->adam_v, P},
-      {&n->bf16_weights, (ispl::net_bf16_bytes() + sizeof(float) - 1) / sizeof(float)}};
+      {&n->bf16_weights, (ispl::net_bf16_bytes() + sizeof(float) - 1) / sizeof(float)},
+      {reinterpret_cast<float**>(&n->select_done), 1}};
   for (auto& a : plan) {
     e = hipMalloc(reinterpret_cast<void**>(a.p), a.n * sizeof(float));
     if (e != hipSuccess) {
@@ -719,6 +721,7 @@ ispl_status ispl_net_create(int32_t device, int32_t max_batch, ispl_net** out) {
     }
   }
   for (float* z : {n->w.params, n->adam_m, n->adam_v}) (void)hipMemset(z, 0, P * sizeof(float));
+  (void)hipMemset(n->select_done, 0, sizeof(int32_t));
   e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     net_free(n);
@@ -910,10 +913,10 @@ ispl_status ispl_net_select(ispl_net* n, const float* logits, int32_t n_gates, i
     return fail(ISPL_ERR_INVALID_ARG, "pointer not 4-byte aligned");
   DeviceGuard guard(n->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = ispl::launch_select_windows(logits, n_gates, fine_len, window_bins, threshold,
-                                             bin_start, confidence, flag, s);
-  if (e == hipSuccess)
-    e = ispl::launch_compact_lists(flag, n_gates, zoom_list, fallback_list, counts, s);
+  const hipError_t e =
+      ispl::launch_select_windows(logits, n_gates, fine_len, window_bins, threshold, bin_start,
+                                  confidence, flag, zoom_list, fallback_list, counts,
+                                  n->select_done, s);
   if (e != hipSuccess) return hip_fail(e, "select launch");
   return ok();
 }
@@ -929,7 +932,6 @@ struct ispl_lzoom {
   int32_t window_bins;
   float threshold;
   float* coarse_spectra;  // [G][1024]
-  float* features;        // [G][1024]
   float* logits;          // [G][1024]
   float* confidence;      // [G]
   float* window_spectra;  // [G][K]
@@ -939,14 +941,15 @@ struct ispl_lzoom {
   int32_t* zoom_list;     // [G]
   int32_t* fallback_list; // [G]
   int32_t* counts;        // [2]: zoomed, fallback
+  int32_t* done;          // completion counter of the decision (zero between calls)
 };
 
 namespace {
 
 void lzoom_free(ispl_lzoom* z) {
-  void* bufs[] = {z->coarse_spectra, z->features, z->logits, z->confidence, z->window_spectra,
+  void* bufs[] = {z->coarse_spectra, z->logits, z->confidence, z->window_spectra,
                   z->full_spectra, z->bin_start, z->flag, z->zoom_list, z->fallback_list,
-                  z->counts};
+                  z->counts, z->done};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (z->zoom) ispl_zoom_destroy(z->zoom);
@@ -996,7 +999,6 @@ ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t win
     void** p;
     int64_t bytes;
   } want[] = {{reinterpret_cast<void**>(&z->coarse_spectra), 4 * G * ispl::NET_LEN},
-              {reinterpret_cast<void**>(&z->features), 4 * G * ispl::NET_LEN},
               {reinterpret_cast<void**>(&z->logits), 4 * G * ispl::NET_LEN},
               {reinterpret_cast<void**>(&z->confidence), 4 * G},
               {reinterpret_cast<void**>(&z->window_spectra), 4 * G * window_bins},
@@ -1005,7 +1007,8 @@ ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t win
               {reinterpret_cast<void**>(&z->flag), 4 * G},
               {reinterpret_cast<void**>(&z->zoom_list), 4 * G},
               {reinterpret_cast<void**>(&z->fallback_list), 4 * G},
-              {reinterpret_cast<void**>(&z->counts), 8}};
+              {reinterpret_cast<void**>(&z->counts), 8},
+              {reinterpret_cast<void**>(&z->done), 4}};
   for (auto& w : want) {
     const hipError_t e = hipMalloc(w.p, static_cast<size_t>(w.bytes));
     if (e != hipSuccess) {
@@ -1013,6 +1016,13 @@ ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t win
       delete z;
       return fail(ISPL_ERR_OUT_OF_MEMORY, "learned-zoom buffers: %s", hipGetErrorString(e));
     }
+  }
+  hipError_t e = hipMemset(z->done, 0, sizeof(int32_t));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    lzoom_free(z);
+    delete z;
+    return hip_fail(e, "learned-zoom init");
   }
   *out = z;
   return ok();
@@ -1043,16 +1053,17 @@ ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx
   ispl_status st = integrate_impl(z->coarse, samples, tx_code, tx_per_pulse, n_pulses, nullptr,
                                   nullptr, z->coarse_spectra, 0, stream);
   if (st != ISPL_OK) return st;
-  // network: features, BF16 logits, windows and the two gate lists
-  hipError_t e = ispl::launch_net_features(z->coarse_spectra, G, z->features, s);
-  if (e == hipSuccess) bf16_table_ready(z->net, s, &e);
+  // network on the coarse spectra (features formed in the kernel), BF16 logits,
+  // windows and the two gate lists
+  hipError_t e;
+  bf16_table_ready(z->net, s, &e);
   if (e == hipSuccess)
-    e = ispl::launch_net_forward_bf16(z->net->bf16_weights, z->features, G, z->logits, s);
+    e = ispl::launch_net_forward_bf16(z->net->bf16_weights, z->coarse_spectra, G, z->logits, s,
+                                      true);
   if (e == hipSuccess)
     e = ispl::launch_select_windows(z->logits, G, c.fft_len, z->window_bins, z->threshold,
-                                    z->bin_start, z->confidence, z->flag, s);
-  if (e == hipSuccess)
-    e = ispl::launch_compact_lists(z->flag, G, z->zoom_list, z->fallback_list, z->counts, s);
+                                    z->bin_start, z->confidence, z->flag, z->zoom_list,
+                                    z->fallback_list, z->counts, z->done, s);
   if (e != hipSuccess) return hip_fail(e, "learned-zoom network launch");
   // zoomed gates: K bins around the proposed centre; the others: full spectra
   st = zoom_impl(z->zoom, samples, tx_code, tx_per_pulse, n_pulses, z->bin_start, z->zoom_list,
@@ -1061,11 +1072,8 @@ ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx
   st = integrate_impl(z->fine, samples, tx_code, tx_per_pulse, n_pulses, z->fallback_list,
                       z->counts + 1, z->full_spectra, 0, stream);
   if (st != ISPL_OK) return st;
-  e = ispl::launch_window_peak(z->window_spectra, G, z->window_bins, c.fft_len, z->bin_start,
-                               z->zoom_list, z->counts, peak_bin, peak_power, s);
-  if (e == hipSuccess)
-    e = ispl::launch_peak(z->full_spectra, G, c.fft_len, 0, c.fft_len, peak_bin, peak_power,
-                          z->fallback_list, z->counts + 1, s);
+  e = ispl::launch_split_peaks(z->window_spectra, z->full_spectra, z->flag, z->bin_start, G,
+                               z->window_bins, c.fft_len, peak_bin, peak_power, s);
   if (e != hipSuccess) return hip_fail(e, "learned-zoom peak launch");
   return ok();
 }

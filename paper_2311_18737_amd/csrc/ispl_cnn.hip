@@ -437,16 +437,27 @@ __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ src, uin
   }
 }
 
+// FROM_SPECTRA: the input rows are coarse spectra and the features
+// log(max(S / mean S, 1e-30)) are formed here (as log_features does).
+template <bool FROM_SPECTRA>
 __global__ void __launch_bounds__(256) net_forward_bf16(const float* __restrict__ x,
                                                         const NetBf16* __restrict__ nw,
                                                         float* __restrict__ logits) {
   __shared__ __attribute__((aligned(16))) float xs[T];
   __shared__ __attribute__((aligned(16))) uint16_t act0[T * 32];
   __shared__ __attribute__((aligned(16))) uint16_t act1[T * 32];
+  __shared__ float red[4];
   const int g = blockIdx.x, j = threadIdx.x, lane = j & 63;
   const int wave = __builtin_amdgcn_readfirstlane(j >> 6);
   const int h = lane >> 5, c = lane & 31;
-  reinterpret_cast<float4*>(xs)[j] = reinterpret_cast<const float4*>(x + static_cast<int64_t>(g) * T)[j];
+  float4 v = reinterpret_cast<const float4*>(x + static_cast<int64_t>(g) * T)[j];
+  if (FROM_SPECTRA) {
+    const float mean = block_sum((v.x + v.y) + (v.z + v.w), red) / static_cast<float>(T);
+    const float inv = 1.f / mean;
+    v = make_float4(logf(fmaxf(v.x * inv, 1e-30f)), logf(fmaxf(v.y * inv, 1e-30f)),
+                    logf(fmaxf(v.z * inv, 1e-30f)), logf(fmaxf(v.w * inv, 1e-30f)));
+  }
+  reinterpret_cast<float4*>(xs)[j] = v;
   __syncthreads();
   // layer 1: one k-step, B[k][t] = bf16(x[t + k - 3]) for k < 7 (lanes h = 1 hold k >= 8: zero)
   {
@@ -516,9 +527,13 @@ hipError_t launch_net_prep_bf16(const float* params, void* table, hipStream_t s)
 }
 
 hipError_t launch_net_forward_bf16(const void* table, const float* x, int batch, float* logits,
-                                   hipStream_t s) {
-  hipLaunchKernelGGL(net_forward_bf16, dim3(batch), dim3(256), 0, s, x,
-                     static_cast<const NetBf16*>(table), logits);
+                                   hipStream_t s, bool from_spectra) {
+  if (from_spectra)
+    hipLaunchKernelGGL(net_forward_bf16<true>, dim3(batch), dim3(256), 0, s, x,
+                       static_cast<const NetBf16*>(table), logits);
+  else
+    hipLaunchKernelGGL(net_forward_bf16<false>, dim3(batch), dim3(256), 0, s, x,
+                       static_cast<const NetBf16*>(table), logits);
   return hipGetLastError();
 }
 

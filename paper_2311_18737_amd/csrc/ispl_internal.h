@@ -112,8 +112,10 @@ hipError_t launch_net_loss_grad(const NetWork& w, const float* x, const float* t
                                 int batch, float* grad, float* loss_mean, hipStream_t s);
 size_t net_bf16_bytes();  // matrix-core weight table of the BF16 forward
 hipError_t launch_net_prep_bf16(const float* params, void* table, hipStream_t s);
+// logits of features x (or, with from_spectra, of coarse spectra x whose
+// features the kernel forms itself)
 hipError_t launch_net_forward_bf16(const void* table, const float* x, int batch, float* logits,
-                                   hipStream_t s);
+                                   hipStream_t s, bool from_spectra = false);
 hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int n, float lr,
                        int step, hipStream_t s);
 
@@ -124,9 +126,13 @@ hipError_t launch_peak(const float* spectra, int32_t n_gates, int32_t n_fft, int
 // Learned-zoom decision kernels.
 hipError_t launch_select_windows(const float* logits, int32_t n_gates, int32_t fine_len,
                                  int32_t window_bins, float threshold, int32_t* bin_start,
-                                 float* confidence, int32_t* flag, hipStream_t s);
-hipError_t launch_compact_lists(const int32_t* flag, int32_t n_gates, int32_t* zoom_list,
-                                int32_t* fallback_list, int32_t* counts, hipStream_t s);
+                                 float* confidence, int32_t* flag, int32_t* zoom_list,
+                                 int32_t* fallback_list, int32_t* counts, int32_t* done,
+                                 hipStream_t s);
+hipError_t launch_split_peaks(const float* window_spectra, const float* full_spectra,
+                              const int32_t* flag, const int32_t* bin_start, int32_t n_gates,
+                              int32_t window_bins, int32_t fine_len, int32_t* peak_bin,
+                              float* peak_power, hipStream_t s);
 hipError_t launch_window_peak(const float* spectra, int32_t n_gates, int32_t window_bins,
                               int32_t fine_len, const int32_t* bin_start, const int32_t* list,
                               const int32_t* count, int32_t* peak_bin, float* peak_power,

@@ -11,7 +11,8 @@
 // Gates with confidence >= threshold take the zoom DFT over their window; the
 // others fall back to the full-resolution spectrum.  Two ordered gate lists
 // (zoomed, fallback) and their counts stay on the device, so the following
-// launches need no host round trip.  The peak search of Section 3.2 then runs
+// launches need no host round trip.  Decision and compaction share one launch
+// (the last workgroup to finish compacts).  The peak search of Section 3.2 then runs
 // over each gate's window or full row.
 
 #include <hip/hip_runtime.h>
@@ -67,10 +68,50 @@ __device__ float block_sum(float x, float* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Ordered compaction of the flags into the zoomed and fallback gate lists by
+// one workgroup of NT threads sweeping the gates in order.
+__device__ void compact_gates(const int32_t* flag, int32_t n_gates, int32_t* zoom_list,
+                              int32_t* fallback_list, int32_t* counts, int* wtot) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int done_zoom = 0;  // zoomed gates before this sweep step (uniform)
+  for (int b0 = 0; b0 < n_gates; b0 += NT) {
+    const int g = b0 + tid;
+    const bool live = g < n_gates;
+    const bool z = live && flag[g] != 0;
+    const uint64_t mask = __ballot(z);
+    const int below = __popcll(mask & ((uint64_t{1} << lane) - 1));
+    __syncthreads();
+    if (lane == 0) wtot[wave] = __popcll(mask);
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+      before += w < wave ? wtot[w] : 0;
+      all += wtot[w];
+    }
+    const int zi = done_zoom + before + below;  // zoomed gates before g
+    if (z)
+      zoom_list[zi] = g;
+    else if (live)
+      fallback_list[g - zi] = g;
+    done_zoom += all;
+  }
+  if (tid == 0) {
+    counts[0] = done_zoom;
+    counts[1] = n_gates - done_zoom;
+  }
+}
+
+// One workgroup per gate decides its window; the workgroup that finishes
+// last (a device-scope counter, reset by that workgroup for the next call)
+// compacts the lists, so decision and lists take one launch.
 __global__ void __launch_bounds__(NT)
-select_windows(const float* __restrict__ logits, int32_t fine_len, int32_t window_bins,
-               float threshold, int32_t* __restrict__ bin_start, float* __restrict__ confidence,
-               int32_t* __restrict__ flag) {
+select_windows(const float* __restrict__ logits, int32_t n_gates, int32_t fine_len,
+               int32_t window_bins, float threshold, int32_t* __restrict__ bin_start,
+               float* __restrict__ confidence, int32_t* __restrict__ flag,
+               int32_t* __restrict__ zoom_list, int32_t* __restrict__ fallback_list,
+               int32_t* __restrict__ counts, int32_t* __restrict__ done) {
+  __shared__ int is_last;
+  __shared__ int wtot[NT / 64];
   __shared__ float sv[NT / 64];
   __shared__ int sk[NT / 64];
   __shared__ float red[NT / 64];
@@ -124,42 +165,14 @@ select_windows(const float* __restrict__ logits, int32_t fine_len, int32_t windo
     const bool ok = conf >= threshold;  // false for NaN
     if (confidence) confidence[g] = conf;
     flag[g] = ok ? 1 : 0;
+    __threadfence();  // release this gate's outputs before counting it
+    is_last = atomicAdd(done, 1) == n_gates - 1;
   }
-}
-
-// Ordered compaction of the flags into the zoomed and fallback gate lists.
-// One workgroup of 1024 threads sweeps the gates in order.
-__global__ void __launch_bounds__(1024)
-compact_lists(const int32_t* __restrict__ flag, int32_t n_gates, int32_t* __restrict__ zoom_list,
-              int32_t* __restrict__ fallback_list, int32_t* __restrict__ counts) {
-  __shared__ int wtot[16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  int done_zoom = 0;  // zoomed gates before this sweep step (uniform)
-  for (int b0 = 0; b0 < n_gates; b0 += 1024) {
-    const int g = b0 + tid;
-    const bool live = g < n_gates;
-    const bool z = live && flag[g] != 0;
-    const uint64_t mask = __ballot(z);
-    const int below = __popcll(mask & ((uint64_t{1} << lane) - 1));
-    __syncthreads();
-    if (lane == 0) wtot[wave] = __popcll(mask);
-    __syncthreads();
-    int before = 0, all = 0;
-    for (int w = 0; w < 16; ++w) {
-      before += w < wave ? wtot[w] : 0;
-      all += wtot[w];
-    }
-    const int zi = done_zoom + before + below;  // zoomed gates before g
-    if (z)
-      zoom_list[zi] = g;
-    else if (live)
-      fallback_list[g - zi] = g;
-    done_zoom += all;
-  }
-  if (tid == 0) {
-    counts[0] = done_zoom;
-    counts[1] = n_gates - done_zoom;
-  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();  // acquire every other workgroup's flag
+  compact_gates(flag, n_gates, zoom_list, fallback_list, counts, wtot);
+  if (j == 0) *done = 0;
 }
 
 // Peak of each listed gate's window: (value, -local index) maximum of row g
@@ -197,20 +210,67 @@ window_peak(const float* __restrict__ spectra, int32_t n_gates, int32_t window_b
   }
 }
 
+// Peak of every gate of the learned zoom: over its window when it was zoomed,
+// over the whole full-resolution row otherwise (ties to the lowest bin, NaN
+// never wins).
+__global__ void __launch_bounds__(NT)
+split_peaks(const float* __restrict__ window_spectra, const float* __restrict__ full_spectra,
+            const int32_t* __restrict__ flag, const int32_t* __restrict__ bin_start,
+            int32_t window_bins, int32_t fine_len, int32_t* __restrict__ peak_bin,
+            float* __restrict__ peak_power) {
+  __shared__ float sv[NT / 64];
+  __shared__ int sk[NT / 64];
+  const int g = blockIdx.x;
+  const bool zoomed = flag[g] != 0;
+  const int len = zoomed ? window_bins : fine_len;
+  const float* row = zoomed ? window_spectra + static_cast<int64_t>(g) * window_bins
+                            : full_spectra + static_cast<int64_t>(g) * fine_len;
+  float bv = -INFINITY;
+  int bk = INT_MAX;
+  for (int i = threadIdx.x; i < len; i += NT) {
+    const float v = row[i];
+    if (better(v, i, bv, bk)) {
+      bv = v;
+      bk = i;
+    }
+  }
+  block_argmax(bv, bk, sv, sk);
+  if (threadIdx.x == 0) {
+    if (bk == INT_MAX) {  // only NaN
+      bk = 0;
+      bv = row[0];
+    }
+    int64_t b = bk;
+    if (zoomed) {
+      int64_t st = bin_start[g] % fine_len;
+      if (st < 0) st += fine_len;
+      b = (st + bk) % fine_len;
+    }
+    peak_bin[g] = static_cast<int32_t>(b);
+    if (peak_power) peak_power[g] = bv;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_select_windows(const float* logits, int32_t n_gates, int32_t fine_len,
                                  int32_t window_bins, float threshold, int32_t* bin_start,
-                                 float* confidence, int32_t* flag, hipStream_t s) {
+                                 float* confidence, int32_t* flag, int32_t* zoom_list,
+                                 int32_t* fallback_list, int32_t* counts, int32_t* done,
+                                 hipStream_t s) {
   hipLaunchKernelGGL(select_windows, dim3(static_cast<unsigned>(n_gates)), dim3(NT), 0, s, logits,
-                     fine_len, window_bins, threshold, bin_start, confidence, flag);
+                     n_gates, fine_len, window_bins, threshold, bin_start, confidence, flag,
+                     zoom_list, fallback_list, counts, done);
   return hipGetLastError();
 }
 
-hipError_t launch_compact_lists(const int32_t* flag, int32_t n_gates, int32_t* zoom_list,
-                                int32_t* fallback_list, int32_t* counts, hipStream_t s) {
-  hipLaunchKernelGGL(compact_lists, dim3(1), dim3(1024), 0, s, flag, n_gates, zoom_list,
-                     fallback_list, counts);
+hipError_t launch_split_peaks(const float* window_spectra, const float* full_spectra,
+                              const int32_t* flag, const int32_t* bin_start, int32_t n_gates,
+                              int32_t window_bins, int32_t fine_len, int32_t* peak_bin,
+                              float* peak_power, hipStream_t s) {
+  hipLaunchKernelGGL(split_peaks, dim3(static_cast<unsigned>(n_gates)), dim3(NT), 0, s,
+                     window_spectra, full_spectra, flag, bin_start, window_bins, fine_len, peak_bin,
+                     peak_power);
   return hipGetLastError();
 }
 
