@@ -320,6 +320,45 @@ ispl_status ispl_lzoom_view(const ispl_lzoom* lzoom, ispl_lzoom_buffers* out);
  * NULL is a no-op. */
 void ispl_destroy(ispl_ctx* ctx);
 
+/*
+ * Streaming ingest (the paper's timing scope, Section 4: host rows copied to
+ * the device and integrated, against one echo every 10 ms).  A ring of
+ * n_slots pinned host slots, each holding up to slot_pulses pulse rows
+ * ([slot_pulses][pulse_stride] samples of cfg's sample_type) and their codes
+ * ([slot_pulses][code_len] complex64, or one row when shared).  For each
+ * submitted slot only the samples the gates read (rows [first_gate,
+ * first_gate + (n_gates-1)*gate_step + code_len)) and the codes go to the
+ * device, on the object's own copy stream; the integration is queued on
+ * `stream` after that copy and equals ispl_integrate_spectra of the same
+ * pulses (so a run of submits with accumulate = 1 after the first equals
+ * calling ispl_integrate_spectra batch by batch).  The copy of one slot
+ * overlaps the integration of the previous one.
+ *   ispl_stream_create   cfg as for ispl_create; 1 <= slot_pulses <= max_pulses;
+ *                        2 <= n_slots <= 64.  Allocates the pinned slots, the
+ *                        device buffers and a context of its own.
+ *   ispl_stream_slot_samples / _codes  pinned host pointers of slot i (NULL for
+ *                        a bad slot); owned by the object.
+ *   ispl_stream_wait_slot  blocks until the slot's last copy has finished:
+ *                        call it before writing into a slot that was submitted.
+ *   ispl_stream_submit   0 <= n_pulses <= slot_pulses; spectra device
+ *                        [n_gates][fft_len] as for ispl_integrate_spectra.
+ *   ispl_stream_sync     blocks until every queued copy and integration of
+ *                        the object has finished.
+ * Not thread-safe; one producer thread.
+ */
+typedef struct ispl_stream ispl_stream;
+
+ispl_status ispl_stream_create(const ispl_config* cfg, int32_t slot_pulses, int32_t n_slots,
+                               ispl_stream** out);
+void ispl_stream_destroy(ispl_stream* st);
+void* ispl_stream_slot_samples(ispl_stream* st, int32_t slot);
+float* ispl_stream_slot_codes(ispl_stream* st, int32_t slot);
+ispl_status ispl_stream_wait_slot(ispl_stream* st, int32_t slot);
+ispl_status ispl_stream_submit(ispl_stream* st, int32_t slot, int32_t n_pulses,
+                               int32_t tx_per_pulse, float* spectra, int32_t accumulate,
+                               void* stream);
+ispl_status ispl_stream_sync(ispl_stream* st);
+
 /* Launch plan the library would use for n_pulses pulses with this config;
  * host-only (no device call), for tests and tooling.  Fills, when non-NULL:
  * chunks = number of pulse chunks integrated side by side (1 = no partial

@@ -52,6 +52,13 @@ EXPORTED = (
     "ispl_lzoom_destroy",
     "ispl_lzoom_peaks",
     "ispl_lzoom_view",
+    "ispl_stream_create",
+    "ispl_stream_destroy",
+    "ispl_stream_slot_samples",
+    "ispl_stream_slot_codes",
+    "ispl_stream_wait_slot",
+    "ispl_stream_submit",
+    "ispl_stream_sync",
     "ispl_plan",
     "ispl_status_string",
     "ispl_last_error",
@@ -175,6 +182,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ispl_lzoom_peaks.restype = i32
     lib.ispl_lzoom_view.argtypes = [vp, ctypes.POINTER(IsplLzoomBuffers)]
     lib.ispl_lzoom_view.restype = i32
+    lib.ispl_stream_create.argtypes = [ctypes.POINTER(IsplConfig), i32, i32, ctypes.POINTER(vp)]
+    lib.ispl_stream_create.restype = i32
+    lib.ispl_stream_destroy.argtypes = [vp]
+    lib.ispl_stream_destroy.restype = None
+    lib.ispl_stream_slot_samples.argtypes = [vp, i32]
+    lib.ispl_stream_slot_samples.restype = vp
+    lib.ispl_stream_slot_codes.argtypes = [vp, i32]
+    lib.ispl_stream_slot_codes.restype = vp
+    lib.ispl_stream_wait_slot.argtypes = [vp, i32]
+    lib.ispl_stream_wait_slot.restype = i32
+    lib.ispl_stream_submit.argtypes = [vp, i32, i32, i32, vp, i32, vp]
+    lib.ispl_stream_submit.restype = i32
+    lib.ispl_stream_sync.argtypes = [vp]
+    lib.ispl_stream_sync.restype = i32
     lib.ispl_plan.argtypes = [ctypes.POINTER(IsplConfig), i32, ctypes.POINTER(i32),
                               ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.ispl_plan.restype = i32

@@ -506,3 +506,74 @@ class LearnedZoom:
                 "full_spectra": ((G, N), "<f4")}
         return {k: torch.as_tensor(_DeviceArray(getattr(b, k), shp, ts, self), device=self.device)
                 for k, (shp, ts) in spec.items()}
+
+
+class StreamIngest:
+    """Streaming ingest (ispl_stream_*): pinned host slots that the producer
+    fills with pulse rows, copied to the device (only the samples the gates
+    read) on a copy stream and integrated on the caller's stream."""
+
+    def __init__(self, *, code_len: int, fft_len: int, n_gates: int, gate_step: int = 25,
+                 first_gate: int = 0, pulse_stride: Optional[int] = None,
+                 sample_type: str = "c64", slot_pulses: int, n_slots: int = 3, device: int = 0):
+        import numpy as np
+
+        self._np = np
+        self._lib = load_library()
+        self.cfg = make_config(code_len=code_len, fft_len=fft_len, n_gates=n_gates,
+                               gate_step=gate_step, first_gate=first_gate,
+                               pulse_stride=pulse_stride, sample_type=sample_type,
+                               max_pulses=slot_pulses, device=device)
+        self.device = torch.device("cuda", device)
+        self.sample_type = sample_type
+        self.slot_pulses, self.n_slots = slot_pulses, n_slots
+        h = ctypes.c_void_p()
+        check(self._lib.ispl_stream_create(ctypes.byref(self.cfg), slot_pulses, n_slots,
+                                           ctypes.byref(h)), "ispl_stream_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ispl_stream_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def slot(self, i: int):
+        """(samples, codes): numpy views of slot i's pinned host memory."""
+        np = self._np
+        sp = self._lib.ispl_stream_slot_samples(self._h, i)
+        cp = self._lib.ispl_stream_slot_codes(self._h, i)
+        if not sp or not cp:
+            raise ValueError(f"no slot {i}")
+        P, S, L = self.slot_pulses, self.cfg.pulse_stride, self.cfg.code_len
+        if self.sample_type == "c64":
+            samples = np.ctypeslib.as_array(ctypes.cast(sp, ctypes.POINTER(ctypes.c_float)),
+                                            shape=(P * S * 2,)).view(np.complex64).reshape(P, S)
+        else:
+            samples = np.ctypeslib.as_array(ctypes.cast(sp, ctypes.POINTER(ctypes.c_int16)),
+                                            shape=(P, S, 2))
+        codes = np.ctypeslib.as_array(ctypes.cast(cp, ctypes.POINTER(ctypes.c_float)),
+                                      shape=(P * L * 2,)).view(np.complex64).reshape(P, L)
+        return samples, codes
+
+    def wait_slot(self, i: int) -> None:
+        check(self._lib.ispl_stream_wait_slot(self._h, i), "ispl_stream_wait_slot")
+
+    def submit(self, i: int, n_pulses: int, spectra: torch.Tensor, *, accumulate: bool,
+               tx_per_pulse: bool = True, stream=None) -> None:
+        _require(spectra.device == self.device and spectra.dtype == torch.float32
+                 and spectra.is_contiguous()
+                 and tuple(spectra.shape) == (self.cfg.n_gates, self.cfg.fft_len),
+                 "spectra must be contiguous float32 [n_gates][fft_len] on the device")
+        check(self._lib.ispl_stream_submit(self._h, i, n_pulses, int(tx_per_pulse), _ptr(spectra),
+                                           int(bool(accumulate)),
+                                           ctypes.c_void_p(_stream_handle(stream, self.device))),
+              "ispl_stream_submit")
+
+    def sync(self) -> None:
+        check(self._lib.ispl_stream_sync(self._h), "ispl_stream_sync")

@@ -46,6 +46,21 @@ ispl_status ok() {
   return ISPL_OK;
 }
 
+}  // namespace
+
+namespace ispl {
+// Error reporting for the other host-side translation units.
+ispl_status report(ispl_status s, const char* msg) {
+  if (s == ISPL_OK)
+    g_last_error.clear();
+  else
+    g_last_error = msg;
+  return s;
+}
+}  // namespace ispl
+
+namespace {
+
 ispl_status hip_fail(hipError_t e, const char* what) {
   return fail(ISPL_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }

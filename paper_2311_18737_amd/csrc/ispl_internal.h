@@ -5,7 +5,13 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include "ispl.h"
+
 namespace ispl {
+
+// Sets the calling thread's ispl_last_error() text (cleared for ISPL_OK) and
+// returns s.
+ispl_status report(ispl_status s, const char* msg);
 
 // Points one wave transforms.  A decoded row of L samples is zero-padded to
 // N = R * M and split into R interleaved sub-spectra of M points each, with

@@ -145,6 +145,18 @@ def test_null_context_and_null_pointers(ispl_lib):
     assert ispl_lib.ispl_lzoom_peaks(None, vp(16), vp(16), 1, 1, vp(16), None, None) == 1
     assert ispl_lib.ispl_lzoom_view(None, None) == 1
     ispl_lib.ispl_lzoom_destroy(None)
+    # streaming ingest
+    st = ctypes.c_void_p(99)
+    assert ispl_lib.ispl_stream_create(None, 10, 2, ctypes.byref(st)) == 1 and st.value is None
+    assert ispl_lib.ispl_stream_create(ctypes.byref(cfg()), 0, 2, ctypes.byref(st)) == 1
+    assert ispl_lib.ispl_stream_create(ctypes.byref(cfg()), 10, 1, ctypes.byref(st)) == 1
+    assert ispl_lib.ispl_stream_create(ctypes.byref(cfg()), 10, 2, None) == 1
+    assert ispl_lib.ispl_stream_slot_samples(None, 0) is None
+    assert ispl_lib.ispl_stream_slot_codes(None, 0) is None
+    assert ispl_lib.ispl_stream_wait_slot(None, 0) == 1
+    assert ispl_lib.ispl_stream_submit(None, 0, 1, 1, vp(16), 0, None) == 1
+    assert ispl_lib.ispl_stream_sync(None) == 1
+    ispl_lib.ispl_stream_destroy(None)
 
 
 def test_create_without_gpu_reports_device_error(ispl_lib):
