@@ -321,6 +321,63 @@ ispl_status ispl_lzoom_view(const ispl_lzoom* lzoom, ispl_lzoom_buffers* out);
 void ispl_destroy(ispl_ctx* ctx);
 
 /*
+ * Uneven batch: several experiments ("modes": different code lengths, FFT
+ * lengths and gate counts on one device) integrated by ONE launch of a HIP
+ * graph whose branches run the modes side by side (or one after another),
+ * so light and heavy modes share the chip without host launches between them.
+ * Each mode computes exactly what ispl_integrate_spectra computes for it; the
+ * plan of each mode (waves per workgroup, pulse chunks) and the graph's shape
+ * come from the project's autotuner.
+ *   ispl_batch_create   1 <= n_modes <= 8 configs (as for ispl_create).
+ *   ispl_batch_io       per mode: samples, tx_code, tx_per_pulse, n_pulses,
+ *                       spectra, with the meanings of ispl_integrate_spectra.
+ *   ispl_batch_integrate  io[n_modes]; accumulate 0/1 for every mode;
+ *                       use_graph = 1 launches the object's graph (captured
+ *                       on first use and again when io, accumulate or the plan
+ *                       change); use_graph = 0 queues the modes' launches on
+ *                       `stream` one after another (a caller may capture that).
+ *   ispl_batch_tune     the autotuner: coordinate descent over each mode's
+ *                       waves per workgroup (bin classes a workgroup computes:
+ *                       the tile shape) and pulse chunks, heaviest mode first,
+ *                       then parallel vs serial branches and the order; each
+ *                       candidate is the graph's median time over `trials`
+ *                       runs on an internal stream.  Keeps and returns the
+ *                       fastest plan and its time (either pointer may be
+ *                       NULL).  It writes the spectra of io.
+ *   ispl_batch_get_plan / set_plan  the plan in use (waves 0 and chunks 0 mean
+ *                       the automatic choice; waves only for modes with
+ *                       L <= 1024: a power of two <= min(16, N/1024)).
+ * Waves per workgroup do not change any result; pulse chunks change the
+ * summation order (results within rounding).  The object owns one context per
+ * mode and its streams; calls on one object must not overlap.
+ */
+typedef struct ispl_batch ispl_batch;
+
+typedef struct {
+  const void* samples;
+  const float* tx_code;
+  int32_t tx_per_pulse;
+  int32_t n_pulses;
+  float* spectra;
+} ispl_batch_io;
+
+typedef struct {
+  int32_t order[8];   /* launch order of the modes (their order on serial branches) */
+  int32_t waves[8];   /* per mode: waves per workgroup, 0 = automatic */
+  int32_t chunks[8];  /* per mode: pulse chunks, 0 = automatic */
+  int32_t serial;     /* 0: one parallel branch per mode; 1: one branch in `order` */
+} ispl_batch_plan;
+
+ispl_status ispl_batch_create(const ispl_config* cfgs, int32_t n_modes, ispl_batch** out);
+void ispl_batch_destroy(ispl_batch* batch);
+ispl_status ispl_batch_integrate(ispl_batch* batch, const ispl_batch_io* io,
+                                 int32_t accumulate, int32_t use_graph, void* stream);
+ispl_status ispl_batch_tune(ispl_batch* batch, const ispl_batch_io* io, int32_t trials,
+                            ispl_batch_plan* best, float* best_ms);
+ispl_status ispl_batch_get_plan(const ispl_batch* batch, ispl_batch_plan* plan);
+ispl_status ispl_batch_set_plan(ispl_batch* batch, const ispl_batch_plan* plan);
+
+/*
  * Streaming ingest (the paper's timing scope, Section 4: host rows copied to
  * the device and integrated, against one echo every 10 ms).  A ring of
  * n_slots pinned host slots, each holding up to slot_pulses pulse rows

@@ -27,7 +27,8 @@ from ._lib import (  # noqa: F401
 
 def __getattr__(name):
     # torch-dependent pieces load lazily so the ABI can be inspected without torch
-    if name in ("Context", "Zoom", "Net", "LearnedZoom", "StreamIngest", "make_config", "plan"):
+    if name in ("Context", "Zoom", "Net", "LearnedZoom", "StreamIngest", "Batch", "make_config",
+                "plan"):
         from . import context
 
         return getattr(context, name)

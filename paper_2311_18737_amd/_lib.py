@@ -59,6 +59,12 @@ EXPORTED = (
     "ispl_stream_wait_slot",
     "ispl_stream_submit",
     "ispl_stream_sync",
+    "ispl_batch_create",
+    "ispl_batch_destroy",
+    "ispl_batch_integrate",
+    "ispl_batch_tune",
+    "ispl_batch_get_plan",
+    "ispl_batch_set_plan",
     "ispl_plan",
     "ispl_status_string",
     "ispl_last_error",
@@ -96,6 +102,21 @@ class IsplLzoomBuffers(ctypes.Structure):
         ("window_spectra", ctypes.c_void_p),
         ("full_spectra", ctypes.c_void_p),
     ]
+
+
+class IsplBatchIO(ctypes.Structure):
+    _fields_ = [
+        ("samples", ctypes.c_void_p),
+        ("tx_code", ctypes.c_void_p),
+        ("tx_per_pulse", ctypes.c_int32),
+        ("n_pulses", ctypes.c_int32),
+        ("spectra", ctypes.c_void_p),
+    ]
+
+
+class IsplBatchPlan(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32 * 8), ("waves", ctypes.c_int32 * 8),
+                ("chunks", ctypes.c_int32 * 8), ("serial", ctypes.c_int32)]
 
 
 class IsplError(RuntimeError):
@@ -196,6 +217,19 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ispl_stream_submit.restype = i32
     lib.ispl_stream_sync.argtypes = [vp]
     lib.ispl_stream_sync.restype = i32
+    lib.ispl_batch_create.argtypes = [ctypes.POINTER(IsplConfig), i32, ctypes.POINTER(vp)]
+    lib.ispl_batch_create.restype = i32
+    lib.ispl_batch_destroy.argtypes = [vp]
+    lib.ispl_batch_destroy.restype = None
+    lib.ispl_batch_integrate.argtypes = [vp, ctypes.POINTER(IsplBatchIO), i32, i32, vp]
+    lib.ispl_batch_integrate.restype = i32
+    lib.ispl_batch_tune.argtypes = [vp, ctypes.POINTER(IsplBatchIO), i32,
+                                    ctypes.POINTER(IsplBatchPlan), ctypes.POINTER(ctypes.c_float)]
+    lib.ispl_batch_tune.restype = i32
+    lib.ispl_batch_get_plan.argtypes = [vp, ctypes.POINTER(IsplBatchPlan)]
+    lib.ispl_batch_get_plan.restype = i32
+    lib.ispl_batch_set_plan.argtypes = [vp, ctypes.POINTER(IsplBatchPlan)]
+    lib.ispl_batch_set_plan.restype = i32
     lib.ispl_plan.argtypes = [ctypes.POINTER(IsplConfig), i32, ctypes.POINTER(i32),
                               ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.ispl_plan.restype = i32

@@ -577,3 +577,103 @@ class StreamIngest:
 
     def sync(self) -> None:
         check(self._lib.ispl_stream_sync(self._h), "ispl_stream_sync")
+
+
+class Batch:
+    """Uneven experiments launched together from one HIP graph (ispl_batch_*).
+    `modes` is a list of geometry dicts (code_len, fft_len, n_gates, gate_step,
+    first_gate, pulse_stride, max_pulses and optionally sample_type)."""
+
+    def __init__(self, modes, *, sample_type: str = "c64", device: int = 0):
+        self._lib = load_library()
+        self.device = torch.device("cuda", device)
+        self.cfgs = (IsplConfig * len(modes))()
+        self.sample_types = []
+        for i, m in enumerate(modes):
+            m = dict(m)
+            st = m.pop("sample_type", sample_type)
+            self.sample_types.append(st)
+            self.cfgs[i] = make_config(sample_type=st, device=device, **m)
+        self.n_modes = len(modes)
+        h = ctypes.c_void_p()
+        check(self._lib.ispl_batch_create(self.cfgs, len(modes), ctypes.byref(h)),
+              "ispl_batch_create")
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.ispl_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _io(self, inputs, outs):
+        _require(len(inputs) == self.n_modes, f"need {self.n_modes} (samples, tx) pairs")
+        io = (_lib.IsplBatchIO * self.n_modes)()
+        res = []
+        for i, (xs, xt) in enumerate(inputs):
+            c = self.cfgs[i]
+            view = Context.__new__(Context)  # only for the sample checks
+            view.cfg, view.device, view.sample_type = c, self.device, self.sample_types[i]
+            n = Context._check_samples(view, xs)
+            if xt.dim() == 1:
+                xt = xt.unsqueeze(0)
+            _require(xt.dtype == torch.complex64 and xt.is_contiguous() and xt.device == self.device
+                     and xt.dim() == 2 and xt.shape[1] == c.code_len,
+                     "tx must be contiguous complex64 [P or 1][code_len] on the device")
+            per_pulse = xt.shape[0] != 1
+            _require(not per_pulse or xt.shape[0] == n, "tx rows must be 1 or n_pulses")
+            out = outs[i] if outs is not None else torch.empty((c.n_gates, c.fft_len),
+                                                               dtype=torch.float32,
+                                                               device=self.device)
+            _require(out.dtype == torch.float32 and out.is_contiguous()
+                     and tuple(out.shape) == (c.n_gates, c.fft_len) and out.device == self.device,
+                     "spectra must be contiguous float32 [n_gates][fft_len] on the device")
+            io[i] = _lib.IsplBatchIO(xs.data_ptr(), xt.data_ptr(), int(per_pulse), n,
+                                     out.data_ptr())
+            res.append(out)
+        return io, res
+
+    def integrate(self, inputs, outs=None, *, accumulate: bool = False, use_graph: bool = True,
+                  stream=None):
+        """inputs: [(samples, tx)] per mode; returns the spectra per mode."""
+        io, res = self._io(inputs, outs)
+        check(self._lib.ispl_batch_integrate(self._h, io, int(bool(accumulate)),
+                                             int(bool(use_graph)),
+                                             ctypes.c_void_p(_stream_handle(stream, self.device))),
+              "ispl_batch_integrate")
+        return res
+
+    def tune(self, inputs, outs=None, trials: int = 3):
+        """Autotune the plan on these inputs (writes their spectra); returns
+        (plan dict, best ms)."""
+        io, _ = self._io(inputs, outs)
+        plan = _lib.IsplBatchPlan()
+        ms = ctypes.c_float()
+        check(self._lib.ispl_batch_tune(self._h, io, trials, ctypes.byref(plan), ctypes.byref(ms)),
+              "ispl_batch_tune")
+        return self._plan_dict(plan), ms.value
+
+    def _plan_dict(self, p) -> dict:
+        n = self.n_modes
+        return {"order": list(p.order)[:n], "waves": list(p.waves)[:n],
+                "chunks": list(p.chunks)[:n], "serial": bool(p.serial)}
+
+    def plan(self) -> dict:
+        p = _lib.IsplBatchPlan()
+        check(self._lib.ispl_batch_get_plan(self._h, ctypes.byref(p)), "ispl_batch_get_plan")
+        return self._plan_dict(p)
+
+    def set_plan(self, order=None, waves=None, chunks=None, serial: bool = False) -> None:
+        p = _lib.IsplBatchPlan()
+        n = self.n_modes
+        for i in range(n):
+            p.order[i] = (order or list(range(n)))[i]
+            p.waves[i] = (waves or [0] * n)[i]
+            p.chunks[i] = (chunks or [0] * n)[i]
+        p.serial = int(bool(serial))
+        check(self._lib.ispl_batch_set_plan(self._h, ctypes.byref(p)), "ispl_batch_set_plan")

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,6 +24,8 @@ struct ispl_ctx {
   int32_t chunks_max;   // largest chunk count any call may plan
   float* twiddle;       // complex64 pairs, N entries
   float* partial;       // chunks_max * G * N floats (nullptr when chunks_max == 1)
+  int32_t force_rw;     // tuned plan (0: automatic): waves per workgroup, L <= 1024 only
+  int32_t force_chunks; // tuned plan (0: automatic): pulse chunks, <= chunks_max
 };
 
 namespace {
@@ -97,12 +100,14 @@ struct Plan {
   int64_t blocks; // workgroups of the fused launch
 };
 
-Plan make_plan(const ispl_config& c, int32_t n_pulses) {
+Plan make_plan(const ispl_config& c, int32_t n_pulses, int32_t force_rw = 0,
+               int32_t force_chunks = 0) {
   Plan pl{};
   pl.sub_len = c.code_len <= ispl::SUB ? ispl::SUB : 16 * ispl::SUB;
   pl.r = c.fft_len / pl.sub_len;
   if (pl.sub_len == ispl::SUB) {  // one wave per bin class
     pl.rw = pl.r < kMaxWavesPerBlock ? pl.r : kMaxWavesPerBlock;
+    if (force_rw > 0 && force_rw < pl.rw) pl.rw = force_rw;  // a power of two dividing R
     pl.zgroups = pl.r / pl.rw;
   } else {                        // sixteen waves per bin class
     pl.rw = 16;
@@ -122,6 +127,7 @@ Plan make_plan(const ispl_config& c, int32_t n_pulses) {
   if (chunks > kMaxChunks) chunks = kMaxChunks;
   const int64_t gn_bytes = static_cast<int64_t>(c.n_gates) * c.fft_len * 4;
   if (chunks > 1 && chunks * gn_bytes > kMaxPartialBytes) chunks = kMaxPartialBytes / gn_bytes;
+  if (force_chunks > 0) chunks = force_chunks < n_pulses ? force_chunks : n_pulses;
   if (chunks < 1) chunks = 1;
   pl.chunks = static_cast<int>(chunks);
   pl.blocks = base * pl.chunks;
@@ -440,7 +446,7 @@ static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const floa
     }
     return ok();
   }
-  const Plan pl = make_plan(c, n_pulses);
+  const Plan pl = make_plan(c, n_pulses, ctx->force_rw, ctx->force_chunks);
   if (pl.chunks > ctx->chunks_max)
     return fail(ISPL_ERR_INVALID_ARG, "internal: plan needs %d chunks > %d", pl.chunks,
                 ctx->chunks_max);
@@ -1107,6 +1113,317 @@ ispl_status ispl_lzoom_view(const ispl_lzoom* z, ispl_lzoom_buffers* out) {
   out->counts = z->counts;
   out->window_spectra = z->window_spectra;
   out->full_spectra = z->full_spectra;
+  return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Uneven batch: several experiments launched together from one HIP graph.
+
+struct ispl_batch {
+  int32_t n_modes;
+  int32_t device;
+  ispl_ctx* ctx[ispl::MAX_BATCH_MODES];
+  hipStream_t branch[ispl::MAX_BATCH_MODES];  // capture streams of the parallel branches
+  hipStream_t cap;
+  hipEvent_t fork, join[ispl::MAX_BATCH_MODES];
+  ispl_batch_plan plan;
+  ispl_batch_io cached[ispl::MAX_BATCH_MODES];
+  int32_t cached_acc;
+  hipGraphExec_t exec;
+  bool graph_valid;
+};
+
+namespace {
+
+void batch_free(ispl_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  for (int i = 0; i < b->n_modes; ++i) {
+    if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
+    if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    if (b->ctx[i]) ispl_destroy(b->ctx[i]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+}
+
+void apply_plan(ispl_batch* b) {
+  for (int m = 0; m < b->n_modes; ++m) {
+    b->ctx[m]->force_rw = b->plan.waves[m];
+    b->ctx[m]->force_chunks = b->plan.chunks[m];
+  }
+}
+
+ispl_status batch_run(ispl_batch* b, const ispl_batch_io* io, int32_t accumulate,
+                      hipStream_t s) {
+  for (int k = 0; k < b->n_modes; ++k) {
+    const int m = b->plan.order[k];
+    const ispl_status st = integrate_impl(b->ctx[m], io[m].samples, io[m].tx_code,
+                                          io[m].tx_per_pulse, io[m].n_pulses, nullptr, nullptr,
+                                          io[m].spectra, accumulate, s);
+    if (st != ISPL_OK) {
+      const std::string why = g_last_error;
+      return fail(st, "mode %d: %s", m, why.c_str());
+    }
+  }
+  return ISPL_OK;
+}
+
+// Captures every mode's launches: on parallel branches (fork / join events)
+// or one after another in plan order, then instantiates the graph.
+ispl_status batch_capture(ispl_batch* b, const ispl_batch_io* io, int32_t accumulate) {
+  if (b->exec) {
+    (void)hipGraphExecDestroy(b->exec);
+    b->exec = nullptr;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "batch capture");
+  ispl_status st = ISPL_OK;
+  if (b->plan.serial) {
+    st = batch_run(b, io, accumulate, b->cap);
+  } else {
+    e = hipEventRecord(b->fork, b->cap);
+    for (int k = 0; k < b->n_modes && e == hipSuccess && st == ISPL_OK; ++k) {
+      const int m = b->plan.order[k];
+      e = hipStreamWaitEvent(b->branch[m], b->fork, 0);
+      if (e != hipSuccess) break;
+      st = integrate_impl(b->ctx[m], io[m].samples, io[m].tx_code, io[m].tx_per_pulse,
+                          io[m].n_pulses, nullptr, nullptr, io[m].spectra, accumulate,
+                          b->branch[m]);
+      if (st == ISPL_OK) e = hipEventRecord(b->join[m], b->branch[m]);
+      if (e == hipSuccess && st == ISPL_OK) e = hipStreamWaitEvent(b->cap, b->join[m], 0);
+    }
+  }
+  const hipError_t ee = hipStreamEndCapture(b->cap, &g);
+  if (e == hipSuccess) e = ee;
+  if (st == ISPL_OK && e == hipSuccess) e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (g) (void)hipGraphDestroy(g);
+  if (st != ISPL_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "batch graph");
+  for (int m = 0; m < b->n_modes; ++m) b->cached[m] = io[m];
+  b->cached_acc = accumulate;
+  b->graph_valid = true;
+  return ISPL_OK;
+}
+
+bool same_io(const ispl_batch_io& x, const ispl_batch_io& y) {
+  return x.samples == y.samples && x.tx_code == y.tx_code && x.tx_per_pulse == y.tx_per_pulse &&
+         x.n_pulses == y.n_pulses && x.spectra == y.spectra;
+}
+
+}  // namespace
+
+extern "C" {
+
+ispl_status ispl_batch_create(const ispl_config* cfgs, int32_t n_modes, ispl_batch** out) {
+  if (!out) return fail(ISPL_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!cfgs) return fail(ISPL_ERR_INVALID_ARG, "configs are NULL");
+  if (n_modes < 1 || n_modes > ispl::MAX_BATCH_MODES)
+    return fail(ISPL_ERR_INVALID_ARG, "n_modes %d outside [1, %d]", n_modes,
+                ispl::MAX_BATCH_MODES);
+  for (int m = 0; m < n_modes; ++m) {
+    const ispl_status st = validate_config(&cfgs[m]);
+    if (st != ISPL_OK) return st;
+    if (cfgs[m].device != cfgs[0].device)
+      return fail(ISPL_ERR_INVALID_ARG, "mode %d: all modes need one device", m);
+  }
+  ispl_batch* b = new (std::nothrow) ispl_batch{};
+  if (!b) return fail(ISPL_ERR_OUT_OF_MEMORY, "host allocation");
+  b->n_modes = n_modes;
+  b->device = cfgs[0].device;
+  for (int m = 0; m < n_modes; ++m) {
+    const ispl_status st = ispl_create(&cfgs[m], &b->ctx[m]);
+    if (st != ISPL_OK) {
+      const std::string why = g_last_error;
+      batch_free(b);
+      delete b;
+      return fail(st, "mode %d: %s", m, why.c_str());
+    }
+    b->plan.order[m] = m;
+  }
+  DeviceGuard guard(b->device);
+  hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+  for (int m = 0; m < n_modes && e == hipSuccess; ++m) {
+    e = hipStreamCreateWithFlags(&b->branch[m], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join[m], hipEventDisableTiming);
+  }
+  if (e != hipSuccess) {
+    batch_free(b);
+    delete b;
+    return hip_fail(e, "batch setup");
+  }
+  *out = b;
+  return ok();
+}
+
+void ispl_batch_destroy(ispl_batch* b) {
+  if (!b) return;
+  {
+    DeviceGuard guard(b->device);
+    (void)hipDeviceSynchronize();
+    batch_free(b);
+  }
+  delete b;
+}
+
+ispl_status ispl_batch_integrate(ispl_batch* b, const ispl_batch_io* io, int32_t accumulate,
+                                 int32_t use_graph, void* stream) {
+  if (!b || !io) return fail(ISPL_ERR_INVALID_ARG, "batch or io is NULL");
+  if ((accumulate != 0 && accumulate != 1) || (use_graph != 0 && use_graph != 1))
+    return fail(ISPL_ERR_INVALID_ARG, "accumulate and use_graph must be 0 or 1");
+  DeviceGuard guard(b->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!use_graph) {
+    const ispl_status st = batch_run(b, io, accumulate, s);
+    return st == ISPL_OK ? ok() : st;
+  }
+  bool same = b->graph_valid && b->cached_acc == accumulate;
+  for (int m = 0; m < b->n_modes && same; ++m) same = same_io(io[m], b->cached[m]);
+  if (!same) {
+    const ispl_status st = batch_capture(b, io, accumulate);
+    if (st != ISPL_OK) return st;
+  }
+  const hipError_t e = hipGraphLaunch(b->exec, s);
+  if (e != hipSuccess) return hip_fail(e, "batch graph launch");
+  return ok();
+}
+
+ispl_status ispl_batch_get_plan(const ispl_batch* b, ispl_batch_plan* plan) {
+  if (!b || !plan) return fail(ISPL_ERR_INVALID_ARG, "NULL argument");
+  *plan = b->plan;
+  return ok();
+}
+
+ispl_status ispl_batch_set_plan(ispl_batch* b, const ispl_batch_plan* plan) {
+  if (!b || !plan) return fail(ISPL_ERR_INVALID_ARG, "NULL argument");
+  bool seen[ispl::MAX_BATCH_MODES] = {};
+  for (int k = 0; k < b->n_modes; ++k) {
+    const int m = plan->order[k];
+    if (m < 0 || m >= b->n_modes || seen[m])
+      return fail(ISPL_ERR_INVALID_ARG, "order is not a permutation of the %d modes", b->n_modes);
+    seen[m] = true;
+  }
+  for (int m = 0; m < b->n_modes; ++m) {
+    const ispl_config& c = b->ctx[m]->cfg;
+    const int w = plan->waves[m];
+    const int r = c.fft_len / ispl::SUB;
+    if (w != 0 && (c.code_len > ispl::SUB || !is_pow2(w) || w > 16 || w > r))
+      return fail(ISPL_ERR_INVALID_ARG, "mode %d: waves %d not a power of two <= min(16, N/1024) "
+                  "(or the mode has L > 1024)", m, w);
+    if (plan->chunks[m] < 0 || plan->chunks[m] > b->ctx[m]->chunks_max)
+      return fail(ISPL_ERR_INVALID_ARG, "mode %d: chunks %d outside [0, %d]", m, plan->chunks[m],
+                  b->ctx[m]->chunks_max);
+  }
+  if (plan->serial != 0 && plan->serial != 1)
+    return fail(ISPL_ERR_INVALID_ARG, "serial must be 0 or 1");
+  b->plan = *plan;
+  apply_plan(b);
+  b->graph_valid = false;
+  return ok();
+}
+
+ispl_status ispl_batch_tune(ispl_batch* b, const ispl_batch_io* io, int32_t trials,
+                            ispl_batch_plan* best, float* best_ms) {
+  if (!b || !io) return fail(ISPL_ERR_INVALID_ARG, "batch or io is NULL");
+  if (trials < 1 || trials > 100)
+    return fail(ISPL_ERR_INVALID_ARG, "trials %d outside [1, 100]", trials);
+  DeviceGuard guard(b->device);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(e, "tune events");
+  hipStream_t s = b->cap;
+  // median time of the batch under a plan, launched from its graph
+  auto measure = [&](const ispl_batch_plan& p, float* ms) -> ispl_status {
+    b->plan = p;
+    apply_plan(b);
+    ispl_status st = batch_capture(b, io, 0);
+    if (st != ISPL_OK) return st;
+    std::vector<float> t;
+    for (int r = 0; r <= trials; ++r) {
+      hipError_t ee = hipEventRecord(e0, s);
+      if (ee == hipSuccess) ee = hipGraphLaunch(b->exec, s);
+      if (ee == hipSuccess) ee = hipEventRecord(e1, s);
+      if (ee == hipSuccess) ee = hipEventSynchronize(e1);
+      float x = 0.f;
+      if (ee == hipSuccess) ee = hipEventElapsedTime(&x, e0, e1);
+      if (ee != hipSuccess) return hip_fail(ee, "tune run");
+      if (r > 0) t.push_back(x);  // the first run warms up
+    }
+    std::sort(t.begin(), t.end());
+    *ms = t[t.size() / 2];
+    return ISPL_OK;
+  };
+  const ispl_batch_plan saved = b->plan;
+  ispl_batch_plan cur = saved;
+  float cur_ms = 0.f;
+  ispl_status st = measure(cur, &cur_ms);
+  // coordinate descent, heaviest mode (most spectra x transform length) first:
+  // waves per workgroup (the tile shape: bin classes per workgroup) and pulse
+  // chunks of each mode, then branch topology and launch order
+  std::vector<int> by_work(b->n_modes);
+  for (int m = 0; m < b->n_modes; ++m) by_work[m] = m;
+  auto work = [&](int m) {
+    const ispl_config& c = b->ctx[m]->cfg;
+    return static_cast<double>(c.n_gates) * c.fft_len * (io[m].n_pulses > 0 ? io[m].n_pulses : 1);
+  };
+  std::sort(by_work.begin(), by_work.end(), [&](int x, int y) { return work(x) > work(y); });
+  for (int m : by_work) {
+    if (st != ISPL_OK) break;
+    const ispl_config& c = b->ctx[m]->cfg;
+    const Plan auto_pl = make_plan(c, io[m].n_pulses > 0 ? io[m].n_pulses : 1);
+    std::vector<std::pair<int, int>> cands;  // (waves, chunks)
+    if (c.code_len <= ispl::SUB)
+      for (int w = auto_pl.rw; w >= 1 && w >= auto_pl.rw / 4; w /= 2) cands.push_back({w, 0});
+    cands.push_back({0, 1});
+    if (auto_pl.chunks > 2) cands.push_back({0, auto_pl.chunks / 2});
+    if (2 * auto_pl.chunks <= b->ctx[m]->chunks_max) cands.push_back({0, 2 * auto_pl.chunks});
+    for (const auto& wc : cands) {
+      ispl_batch_plan p = cur;
+      p.waves[m] = wc.first == auto_pl.rw ? 0 : wc.first;
+      p.chunks[m] = wc.second;
+      if (p.waves[m] == cur.waves[m] && p.chunks[m] == cur.chunks[m]) continue;
+      float ms = 0.f;
+      st = measure(p, &ms);
+      if (st != ISPL_OK) break;
+      if (ms < cur_ms) {
+        cur = p;
+        cur_ms = ms;
+      }
+    }
+  }
+  if (st == ISPL_OK) {
+    ispl_batch_plan p = cur;
+    p.serial = 1 - cur.serial;
+    float ms = 0.f;
+    st = measure(p, &ms);
+    if (st == ISPL_OK && ms < cur_ms) {
+      cur = p;
+      cur_ms = ms;
+    }
+  }
+  if (st == ISPL_OK && cur.serial) {  // heaviest first, and the given order
+    ispl_batch_plan p = cur;
+    for (int k = 0; k < b->n_modes; ++k) p.order[k] = by_work[k];
+    float ms = 0.f;
+    st = measure(p, &ms);
+    if (st == ISPL_OK && ms < cur_ms) {
+      cur = p;
+      cur_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->plan = st == ISPL_OK ? cur : saved;
+  apply_plan(b);
+  b->graph_valid = false;
+  if (st != ISPL_OK) return st;
+  if (best) *best = cur;
+  if (best_ms) *best_ms = cur_ms;
   return ok();
 }
 

@@ -44,6 +44,8 @@ struct FusedArgs {
   const int32_t* gate_count; // device int32, read by the kernels
 };
 
+constexpr int MAX_BATCH_MODES = 8;
+
 // Static LDS bytes of one fused workgroup with `rw` waves and sub-transform M.
 int fused_lds_bytes(int rw, int sub_len);
 

@@ -116,6 +116,20 @@ CONFIGS = {
         name="paper", cfg_id=6, n_pulses=100, n_gates=4096, code_len=16384,
         fft_len=16384, sample_type="c64", f_peak_hz=(6e6, 6e6), snr_db=-10.0,
         echo_stride=64),
+    # uneven batch: four experiments of 500 pulses with different code and FFT
+    # lengths and gate counts, small-workload content (every 8th range echoes)
+    "batch_a": EchoConfig(
+        name="batch_a", cfg_id=11, n_pulses=500, n_gates=200, code_len=128, fft_len=4096,
+        sample_type="c64", echo_stride=8),
+    "batch_b": EchoConfig(
+        name="batch_b", cfg_id=12, n_pulses=500, n_gates=600, code_len=480, fft_len=8192,
+        sample_type="c64", echo_stride=8),
+    "batch_c": EchoConfig(
+        name="batch_c", cfg_id=13, n_pulses=500, n_gates=1000, code_len=1000, fft_len=16384,
+        sample_type="c64", echo_stride=8),
+    "batch_d": EchoConfig(
+        name="batch_d", cfg_id=14, n_pulses=500, n_gates=2000, code_len=2000, fft_len=32768,
+        sample_type="c64", echo_stride=8),
     # learned-zoom workload: the small shape with N = 16384 (1024-bin coarse
     # spectra feed the window-proposal network), independent lines per gate
     "zoom": EchoConfig(

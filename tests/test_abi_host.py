@@ -157,6 +157,17 @@ def test_null_context_and_null_pointers(ispl_lib):
     assert ispl_lib.ispl_stream_submit(None, 0, 1, 1, vp(16), 0, None) == 1
     assert ispl_lib.ispl_stream_sync(None) == 1
     ispl_lib.ispl_stream_destroy(None)
+    # uneven batch
+    bt = ctypes.c_void_p(99)
+    assert ispl_lib.ispl_batch_create(None, 1, ctypes.byref(bt)) == 1 and bt.value is None
+    assert ispl_lib.ispl_batch_create(ctypes.byref(cfg()), 0, ctypes.byref(bt)) == 1
+    assert ispl_lib.ispl_batch_create(ctypes.byref(cfg()), 9, ctypes.byref(bt)) == 1
+    assert ispl_lib.ispl_batch_create(ctypes.byref(cfg()), 1, None) == 1
+    assert ispl_lib.ispl_batch_integrate(None, None, 0, 1, None) == 1
+    assert ispl_lib.ispl_batch_tune(None, None, 3, None, None) == 1
+    assert ispl_lib.ispl_batch_get_plan(None, None) == 1
+    assert ispl_lib.ispl_batch_set_plan(None, None) == 1
+    ispl_lib.ispl_batch_destroy(None)
 
 
 def test_create_without_gpu_reports_device_error(ispl_lib):

@@ -1,0 +1,159 @@
+"""Uneven experiments launched together from one HIP graph (ispl_batch_*).
+
+Four modes with the shapes of the uneven-batch workload scaled down (code
+lengths 128, 480, 1000, 2000; FFT lengths 4096 ... 32768, the last one with
+the long-code transform).  Under the automatic plan every mode runs exactly
+its ispl_integrate_spectra launches, so the batch must reproduce them bit for
+bit, from its graph (parallel or serial branches) and from direct launches;
+other waves per workgroup must not change a bit, other pulse chunks only the
+rounding; against the FP64 oracle every mode meets the plain path's 1e-5 bound.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import integrate_spectra  # noqa: E402
+from synth import random_inputs  # noqa: E402
+from tests.conftest import ensure_library  # noqa: E402
+from tests.parity_util import spectra_error  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+MODES = [  # L, N, G, P
+    (128, 4096, 7, 9),
+    (480, 8192, 5, 12),
+    (1000, 16384, 4, 10),
+    (2000, 32768, 3, 11),
+]
+
+
+@pytest.fixture(scope="module")
+def ispl():
+    ensure_library()
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2311_18737_amd as pkg
+
+    return pkg
+
+
+def make(modes, st="c64", s=25, seed=0):
+    geo, data = [], []
+    for i, (L, N, G, P) in enumerate(modes):
+        g0 = 3 * i
+        stride = g0 + (G - 1) * s + L + 11
+        samples, tx = random_inputs(P, stride, L, sample_type=st, code_kind="bpsk",
+                                    seed=seed + 17 * i, amplitude=3000.0 if st == "ci16" else 1.0)
+        geo.append(dict(code_len=L, fft_len=N, n_gates=G, gate_step=s, first_gate=g0,
+                        pulse_stride=stride, max_pulses=max(P, 1)))
+        data.append((samples, tx))
+    return geo, data
+
+
+def per_mode(ispl, geo, data, st):
+    out = []
+    for g, (samples, tx) in zip(geo, data):
+        ctx = ispl.Context(sample_type=st, **g)
+        out.append(ctx.integrate_spectra(torch.from_numpy(samples).to(DEV),
+                                         torch.from_numpy(tx).to(DEV)))
+        torch.cuda.synchronize()
+        ctx.close()
+    return out
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("st", ["c64", "ci16"])
+def test_batch_equals_each_mode_bit_for_bit(ispl, st):
+    say(f"case {st}")
+    geo, data = make(MODES, st)
+    inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
+    ref = per_mode(ispl, geo, data, st)
+    b = ispl.Batch(geo, sample_type=st)
+    for use_graph in (True, False, True):  # the second graph launch replays the same graph
+        outs = [torch.full_like(r, -1.0) for r in ref]
+        b.integrate(inputs, outs, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for m, (o, r) in enumerate(zip(outs, ref)):
+            assert torch.equal(o, r), (m, use_graph)
+    # accumulate adds every mode's sums once more
+    b.integrate(inputs, outs, accumulate=True)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert torch.equal(o, 2 * r)
+    # the FP64 oracle on every mode
+    for g, (samples, tx), r in zip(geo, data, ref):
+        want = integrate_spectra(samples, tx, n_gates=g["n_gates"], gate_step=g["gate_step"],
+                                 first_gate=g["first_gate"], fft_len=g["fft_len"],
+                                 tx_per_pulse=True)
+        err = spectra_error(r.cpu().numpy(), want)
+        assert err["max_e"] <= 1e-5, (g, err)
+    b.close()
+
+
+def test_autotuner_and_plans(ispl):
+    geo, data = make(MODES, seed=5)
+    inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
+    ref = per_mode(ispl, geo, data, "c64")
+    b = ispl.Batch(geo)
+    plan, ms = b.tune(inputs, trials=2)
+    say(f"  tuned plan {plan}, {ms:.3f} ms")
+    assert sorted(plan["order"]) == [0, 1, 2, 3] and ms > 0
+    assert b.plan() == plan
+    outs = b.integrate(inputs)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        scale = torch.maximum(r, r.mean(dim=1, keepdim=True))
+        assert float(((o - r).abs() / torch.clamp(scale, min=1e-30)).max()) <= 2e-6
+    # other tile shapes (waves per workgroup) and serial branches: bit for bit
+    for waves, serial in (([2, 4, 8, 0], False), ([1, 1, 2, 0], True), ([4, 8, 16, 0], False)):
+        b.set_plan(order=[3, 2, 1, 0], waves=waves, serial=serial)
+        outs = b.integrate(inputs)
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), (waves, serial)
+    for bad in (dict(order=[0, 0, 1, 2]), dict(waves=[3, 0, 0, 0]), dict(waves=[0, 0, 0, 8]),
+                dict(waves=[8, 0, 0, 0]), dict(chunks=[0, 0, 0, 10 ** 6])):
+        with pytest.raises(ispl.IsplError):
+            b.set_plan(**bad)
+    b.close()
+
+
+def test_batch_with_chunked_plans_and_an_empty_mode(ispl):
+    """More pulses: the automatic plans split pulses into chunks, and the batch
+    runs exactly those plans; a mode without pulses gets zero spectra."""
+    modes = [(128, 4096, 7, 40), (480, 8192, 5, 0), (1000, 16384, 4, 33)]
+    geo, data = make(modes, seed=9)
+    inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
+    ref = per_mode(ispl, geo, data, "c64")
+    b = ispl.Batch(geo)
+    outs = [torch.full_like(r, 5.0) for r in ref]
+    b.integrate(inputs, outs)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert torch.equal(o, r)
+    assert torch.count_nonzero(outs[1]).item() == 0
+    b.close()
+
+
+def test_batch_mixed_sample_types(ispl):
+    geo_c, data_c = make(MODES[:2], "c64", seed=3)
+    geo_i, data_i = make(MODES[2:], "ci16", seed=4)
+    geo = [dict(g, sample_type="c64") for g in geo_c] + [dict(g, sample_type="ci16") for g in geo_i]
+    data = data_c + data_i
+    inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
+    ref = per_mode(ispl, geo_c, data_c, "c64") + per_mode(ispl, geo_i, data_i, "ci16")
+    b = ispl.Batch(geo)
+    outs = b.integrate(inputs)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert torch.equal(o, r)
+    b.close()
