@@ -327,7 +327,7 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   using raw_t = typename IO::raw_t;
 
   __shared__ float2 xs[RW * XWAVE];
-  __shared__ float2 ys[DBUF ? 2 : 1][SUB];
+  __shared__ float2 ys[RW == 1 ? 1 : (DBUF ? 2 : 1)][RW == 1 ? 1 : SUB];  // unused for RW = 1
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -377,6 +377,18 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   };
 
   float2* xw = xs + wave * XWAVE;
+  if constexpr (RW == 1) {
+    // One wave owns the gate: thread tid loads samples tid + 64 i, which are
+    // exactly its pass-1 inputs, so the row needs no LDS stage and no barrier;
+    // the other waves on the SIMD hide the load latency.
+    for (int p = p0; p < p1; ++p) {
+      load(p);
+      float2 v[16];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
+      wave_fft_accumulate(v, xw, wt, dk, acc, lane);
+    }
+  } else {
   if (p0 < p1) load(p0);
   for (int p = p0; p < p1; ++p) {
     const int buf = DBUF ? ((p - p0) & 1) : 0;
@@ -389,6 +401,7 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = ys[buf][lane + 64 * j];
     wave_fft_accumulate(v, xw, wt, dk, acc, lane);
+  }
   }
 
   // Stage the sums through LDS in bin order (bin k1 + R kb, k1 = zg RW + wave),
@@ -639,6 +652,7 @@ unsigned grid_for(int64_t elems) {
 
 int fused_lds_bytes(int rw, int sub_len) {
   if (sub_len == 16 * SUB) return static_cast<int>(sizeof(float2)) * 16 * XWAVE;
+  if (rw == 1) return static_cast<int>(sizeof(float2)) * XWAVE;  // no staged row
   return static_cast<int>(sizeof(float2)) * (rw * XWAVE + (rw == 16 ? 2 : 1) * SUB);
 }
 
