@@ -413,6 +413,10 @@ __device__ __forceinline__ void store_tile(const nf32x16& acc, const float* bias
   }
 }
 
+// One 32-channel layer: each wave sweeps its 256 positions as four pairs of
+// 32-position tiles; the two tiles' accumulation chains are interleaved and
+// the B fragments of the next k-step are read from LDS one step ahead, so
+// neither the matrix-core latency nor the LDS latency stalls a lone wave.
 __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ src, uint16_t* __restrict__ dst,
                                            const Frag8 (*__restrict__ wt)[64], const float* bias,
                                            int wave, int lane) {
@@ -420,20 +424,36 @@ __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ src, uin
   Frag8 afr[14];
 #pragma unroll
   for (int ks = 0; ks < 14; ++ks) afr[ks] = wt[ks][lane];
-  for (int tile = 0; tile < 8; ++tile) {
-    const int t = 256 * wave + 32 * tile + c;  // this lane's column
-    nf32x16 acc;
+  auto bfrag = [&](int t, int ks) {
+    const int kk = ks >> 1, ci0 = 16 * (ks & 1) + 8 * h;
+    const int row = (t + kk - PAD) & (T - 1);
+    return *reinterpret_cast<const Frag8*>(src + act_idx(row, ci0));
+  };
+  for (int pair = 0; pair < 4; ++pair) {
+    const int t0 = 256 * wave + 64 * pair + c, t1 = t0 + 32;  // this lane's two columns
+    nf32x16 acc0, acc1;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+    for (int r = 0; r < 16; ++r) {
+      acc0[r] = 0.f;
+      acc1[r] = 0.f;
+    }
+    Frag8 b0 = bfrag(t0, 0), b1 = bfrag(t1, 0);
 #pragma unroll
     for (int ks = 0; ks < 14; ++ks) {
-      const int kk = ks >> 1, ci0 = 16 * (ks & 1) + 8 * h;
-      const int row = (t + kk - PAD) & (T - 1);
-      const Frag8 bfr = *reinterpret_cast<const Frag8*>(src + act_idx(row, ci0));
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, afr[ks]),
-                                                    __builtin_bit_cast(nbf16x8, bfr), acc, 0, 0, 0);
+      Frag8 n0 = b0, n1 = b1;
+      if (ks + 1 < 14) {
+        n0 = bfrag(t0, ks + 1);
+        n1 = bfrag(t1, ks + 1);
+      }
+      acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, afr[ks]),
+                                                     __builtin_bit_cast(nbf16x8, b0), acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, afr[ks]),
+                                                     __builtin_bit_cast(nbf16x8, b1), acc1, 0, 0, 0);
+      b0 = n0;
+      b1 = n1;
     }
-    store_tile(acc, bias, h, t, dst);
+    store_tile(acc0, bias, h, t0, dst);
+    store_tile(acc1, bias, h, t1, dst);
   }
 }
 
