@@ -446,10 +446,10 @@ static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const floa
     }
     return ok();
   }
-  const Plan pl = make_plan(c, n_pulses, ctx->force_rw, ctx->force_chunks);
-  if (pl.chunks > ctx->chunks_max)
-    return fail(ISPL_ERR_INVALID_ARG, "internal: plan needs %d chunks > %d", pl.chunks,
-                ctx->chunks_max);
+  Plan pl = make_plan(c, n_pulses, ctx->force_rw, ctx->force_chunks);
+  // a tuned tile shape can ask for more chunks than the scratch was sized for;
+  // fewer chunks only change how the pulses are split
+  if (pl.chunks > ctx->chunks_max) pl.chunks = ctx->chunks_max;
 
   ispl::FusedArgs a{};
   a.samples = samples;
@@ -1192,8 +1192,9 @@ ispl_status batch_capture(ispl_batch* b, const ispl_batch_io* io, int32_t accumu
       st = integrate_impl(b->ctx[m], io[m].samples, io[m].tx_code, io[m].tx_per_pulse,
                           io[m].n_pulses, nullptr, nullptr, io[m].spectra, accumulate,
                           b->branch[m]);
-      if (st == ISPL_OK) e = hipEventRecord(b->join[m], b->branch[m]);
-      if (e == hipSuccess && st == ISPL_OK) e = hipStreamWaitEvent(b->cap, b->join[m], 0);
+      // rejoin the branch even after an error, so the capture ends cleanly
+      e = hipEventRecord(b->join[m], b->branch[m]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->join[m], 0);
     }
   }
   const hipError_t ee = hipStreamEndCapture(b->cap, &g);
