@@ -398,22 +398,37 @@ __global__ void __launch_bounds__(256) prep_bf16(const float* __restrict__ p, Ne
   if (tid == 0) out->b4 = p[14880];
 }
 
-// bias + ReLU of one 32 x 32 accumulator tile (D[co][t], co = (r % 4) + 8 (r / 4) + 4 h,
-// t = this lane's column), rounded to BF16 and stored as four 8-byte groups.
-__device__ __forceinline__ void store_tile(const nf32x16& acc, const float* bias, int h, int t,
+// The 16 biases of this lane's accumulator rows: bv[r] = bias[co(r)] with
+// co(r) = (r % 4) + 8 (r / 4) + 4 h (h = lane / 32), loaded once per layer.
+__device__ __forceinline__ void load_bias(const float* bias, int h, float (&bv)[16]) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) bv[r] = bias[(r & 3) + 8 * (r >> 2) + 4 * h];
+}
+
+// bias + ReLU of one 32 x 32 accumulator tile (D[co][t], t = this lane's
+// column), rounded to BF16 and stored as four 8-byte groups.
+__device__ __forceinline__ void store_tile(const nf32x16& acc, const float (&bv)[16], int h, int t,
                                            uint16_t* dst) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int co = 8 * q + 4 * h;
-    const uint32_t v01 = to_bf16(fmaxf(acc[4 * q + 0] + bias[co + 0], 0.f)) |
-                         (to_bf16(fmaxf(acc[4 * q + 1] + bias[co + 1], 0.f)) << 16);
-    const uint32_t v23 = to_bf16(fmaxf(acc[4 * q + 2] + bias[co + 2], 0.f)) |
-                         (to_bf16(fmaxf(acc[4 * q + 3] + bias[co + 3], 0.f)) << 16);
+    const uint32_t v01 = to_bf16(fmaxf(acc[4 * q + 0] + bv[4 * q + 0], 0.f)) |
+                         (to_bf16(fmaxf(acc[4 * q + 1] + bv[4 * q + 1], 0.f)) << 16);
+    const uint32_t v23 = to_bf16(fmaxf(acc[4 * q + 2] + bv[4 * q + 2], 0.f)) |
+                         (to_bf16(fmaxf(acc[4 * q + 3] + bv[4 * q + 3], 0.f)) << 16);
     *reinterpret_cast<uint2*>(dst + act_idx(t, co)) = make_uint2(v01, v23);
   }
 }
 
-// One 32-channel layer: each wave sweeps its 256 positions as four pairs of
+// Forward workgroup: FW_WAVES waves, each owning FW_SPAN consecutive positions.
+constexpr int FW_WAVES = 8;
+constexpr int FW_THREADS = 64 * FW_WAVES;
+constexpr int FW_SPAN = T / FW_WAVES;   // 128 positions per wave
+constexpr int FW_PAIRS = FW_SPAN / 64;  // pairs of 32-position tiles per wave
+constexpr int FW_PER_THREAD = T / FW_THREADS;
+static_assert(FW_SPAN % 64 == 0 && T % FW_THREADS == 0, "forward tiling");
+
+// One 32-channel layer: each wave sweeps its positions as pairs of
 // 32-position tiles; the two tiles' accumulation chains are interleaved and
 // the B fragments of the next k-step are read from LDS one step ahead, so
 // neither the matrix-core latency nor the LDS latency stalls a lone wave.
@@ -424,13 +439,15 @@ __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ src, uin
   Frag8 afr[14];
 #pragma unroll
   for (int ks = 0; ks < 14; ++ks) afr[ks] = wt[ks][lane];
+  float bv[16];
+  load_bias(bias, h, bv);
   auto bfrag = [&](int t, int ks) {
     const int kk = ks >> 1, ci0 = 16 * (ks & 1) + 8 * h;
     const int row = (t + kk - PAD) & (T - 1);
     return *reinterpret_cast<const Frag8*>(src + act_idx(row, ci0));
   };
-  for (int pair = 0; pair < 4; ++pair) {
-    const int t0 = 256 * wave + 64 * pair + c, t1 = t0 + 32;  // this lane's two columns
+  for (int pair = 0; pair < FW_PAIRS; ++pair) {
+    const int t0 = FW_SPAN * wave + 64 * pair + c, t1 = t0 + 32;  // this lane's two columns
     nf32x16 acc0, acc1;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -452,38 +469,49 @@ __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ src, uin
       b0 = n0;
       b1 = n1;
     }
-    store_tile(acc0, bias, h, t0, dst);
-    store_tile(acc1, bias, h, t1, dst);
+    store_tile(acc0, bv, h, t0, dst);
+    store_tile(acc1, bv, h, t1, dst);
   }
 }
 
 // FROM_SPECTRA: the input rows are coarse spectra and the features
 // log(max(S / mean S, 1e-30)) are formed here (as log_features does).
 template <bool FROM_SPECTRA>
-__global__ void __launch_bounds__(256) net_forward_bf16(const float* __restrict__ x,
-                                                        const NetBf16* __restrict__ nw,
-                                                        float* __restrict__ logits) {
+__global__ void __launch_bounds__(FW_THREADS) net_forward_bf16(const float* __restrict__ x,
+                                                               const NetBf16* __restrict__ nw,
+                                                               float* __restrict__ logits) {
   __shared__ __attribute__((aligned(16))) float xs[T];
   __shared__ __attribute__((aligned(16))) uint16_t act0[T * 32];
   __shared__ __attribute__((aligned(16))) uint16_t act1[T * 32];
-  __shared__ float red[4];
+  __shared__ float red[FW_WAVES];
+  __shared__ float w4s[32 * TAPS];  // layer-4 weights, read by every lane
   const int g = blockIdx.x, j = threadIdx.x, lane = j & 63;
   const int wave = __builtin_amdgcn_readfirstlane(j >> 6);
   const int h = lane >> 5, c = lane & 31;
-  float4 v = reinterpret_cast<const float4*>(x + static_cast<int64_t>(g) * T)[j];
+  if (j < 32 * TAPS) w4s[j] = nw->w4[j];
+  static_assert(FW_PER_THREAD == 2, "two input values per thread");
+  float2 v = reinterpret_cast<const float2*>(x + static_cast<int64_t>(g) * T)[j];
   if (FROM_SPECTRA) {
-    const float mean = block_sum((v.x + v.y) + (v.z + v.w), red) / static_cast<float>(T);
-    const float inv = 1.f / mean;
-    v = make_float4(logf(fmaxf(v.x * inv, 1e-30f)), logf(fmaxf(v.y * inv, 1e-30f)),
-                    logf(fmaxf(v.z * inv, 1e-30f)), logf(fmaxf(v.w * inv, 1e-30f)));
+    float sum = v.x + v.y;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+    if (lane == 0) red[wave] = sum;
+    __syncthreads();
+    float tot = 0.f;
+#pragma unroll
+    for (int w = 0; w < FW_WAVES; ++w) tot += red[w];  // fixed order
+    const float inv = 1.f / (tot / static_cast<float>(T));
+    v = make_float2(logf(fmaxf(v.x * inv, 1e-30f)), logf(fmaxf(v.y * inv, 1e-30f)));
   }
-  reinterpret_cast<float4*>(xs)[j] = v;
+  reinterpret_cast<float2*>(xs)[j] = v;
   __syncthreads();
   // layer 1: one k-step, B[k][t] = bf16(x[t + k - 3]) for k < 7 (lanes h = 1 hold k >= 8: zero)
   {
     const Frag8 a1 = nw->w1[lane];
-    for (int tile = 0; tile < 8; ++tile) {
-      const int t = 256 * wave + 32 * tile + c;
+    float bv[16];
+    load_bias(nw->b1, h, bv);
+    for (int tile = 0; tile < FW_SPAN / 32; ++tile) {
+      const int t = FW_SPAN * wave + 32 * tile + c;
       Frag8 bfr;
 #pragma unroll
       for (int i = 0; i < 8; i += 2) {
@@ -499,7 +527,7 @@ __global__ void __launch_bounds__(256) net_forward_bf16(const float* __restrict_
       for (int r = 0; r < 16; ++r) acc[r] = 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, a1),
                                                     __builtin_bit_cast(nbf16x8, bfr), acc, 0, 0, 0);
-      store_tile(acc, nw->b1, h, t, act0);
+      store_tile(acc, bv, h, t, act0);
     }
   }
   __syncthreads();
@@ -507,24 +535,24 @@ __global__ void __launch_bounds__(256) net_forward_bf16(const float* __restrict_
   __syncthreads();
   mfma_layer(act1, act0, nw->w3, nw->b3, wave, lane);
   __syncthreads();
-  // layer 4: thread j computes positions t = j + 256 m (consecutive lanes read
-  // consecutive rows: conflict-free 16-byte LDS reads)
+  // layer 4: thread j computes positions t = j + FW_THREADS m (consecutive lanes
+  // read consecutive rows: conflict-free 16-byte LDS reads)
   float* out = logits + static_cast<int64_t>(g) * T;
-  float acc[4];
+  float acc[FW_PER_THREAD];
 #pragma unroll
-  for (int m = 0; m < 4; ++m) acc[m] = nw->b4;
+  for (int m = 0; m < FW_PER_THREAD; ++m) acc[m] = nw->b4;
 #pragma unroll 1
   for (int q = 0; q < 4; ++q) {
 #pragma unroll
     for (int kk = 0; kk < TAPS; ++kk) {
       float w[8];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) w[i] = nw->w4[(8 * q + i) * TAPS + kk];
+      for (int i = 0; i < 8; ++i) w[i] = w4s[(8 * q + i) * TAPS + kk];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int row = (j + 256 * m + kk - PAD) & (T - 1);
-        const uint4 v = *reinterpret_cast<const uint4*>(act0 + act_idx(row, 8 * q));
-        const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+      for (int m = 0; m < FW_PER_THREAD; ++m) {
+        const int row = (j + FW_THREADS * m + kk - PAD) & (T - 1);
+        const uint4 u4 = *reinterpret_cast<const uint4*>(act0 + act_idx(row, 8 * q));
+        const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           acc[m] = fmaf(w[2 * i], __uint_as_float(u[i] << 16), acc[m]);
@@ -534,7 +562,7 @@ __global__ void __launch_bounds__(256) net_forward_bf16(const float* __restrict_
     }
   }
 #pragma unroll
-  for (int m = 0; m < 4; ++m) out[j + 256 * m] = acc[m];
+  for (int m = 0; m < FW_PER_THREAD; ++m) out[j + FW_THREADS * m] = acc[m];
 }
 
 }  // namespace
@@ -549,10 +577,10 @@ hipError_t launch_net_prep_bf16(const float* params, void* table, hipStream_t s)
 hipError_t launch_net_forward_bf16(const void* table, const float* x, int batch, float* logits,
                                    hipStream_t s, bool from_spectra) {
   if (from_spectra)
-    hipLaunchKernelGGL(net_forward_bf16<true>, dim3(batch), dim3(256), 0, s, x,
+    hipLaunchKernelGGL(net_forward_bf16<true>, dim3(batch), dim3(FW_THREADS), 0, s, x,
                        static_cast<const NetBf16*>(table), logits);
   else
-    hipLaunchKernelGGL(net_forward_bf16<false>, dim3(batch), dim3(256), 0, s, x,
+    hipLaunchKernelGGL(net_forward_bf16<false>, dim3(batch), dim3(FW_THREADS), 0, s, x,
                        static_cast<const NetBf16*>(table), logits);
   return hipGetLastError();
 }
