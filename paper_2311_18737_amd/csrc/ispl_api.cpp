@@ -290,8 +290,8 @@ struct ZoomPlan {
 
 // Bins per workgroup: 256 when K allows it (each staged sample feeds twice the
 // matrix work), else 128.  Pulse chunks until there are two workgroups per
-// compute unit, but at least 24 pulses per chunk; column tiles to fit a chunk
-// (at most 2 with 256 bins: 128 accumulator registers would spill).
+// compute unit, but at least 24 pulses per chunk; one or two 32-pulse column
+// tiles per block (more, with the prefetched samples, would spill).
 ZoomPlan zoom_plan(int32_t n_gates, int32_t n_bins, int32_t n_pulses) {
   ZoomPlan z{};
   z.rt = n_bins % 256 == 0 ? 2 : 1;
@@ -301,8 +301,7 @@ ZoomPlan zoom_plan(int32_t n_gates, int32_t n_bins, int32_t n_pulses) {
   if (chunks > by_pulses) chunks = by_pulses;
   z.chunks = static_cast<int>(chunks);
   const int64_t per = (n_pulses + chunks - 1) / chunks;
-  z.ct = per <= 32 ? 1 : (per <= 64 ? 2 : 4);
-  if (z.rt == 2 && z.ct > 2) z.ct = 2;  // 2 x 4 accumulator tiles would spill
+  z.ct = per <= 32 ? 1 : 2;  // more column tiles per block would spill
   return z;
 }
 

@@ -89,7 +89,7 @@ struct ZoomArgs {
   int32_t precision;        // 0: BF16 x3, 1: FP16 x3
   int32_t chunks;           // pulse chunks (workgroups per gate and bin tile)
   int32_t row_tiles;        // RT: 1 or 2 (128 or 256 bins per workgroup)
-  int32_t col_tiles;        // CT: 1, 2 or 4 (32, 64 or 128 pulses per block)
+  int32_t col_tiles;        // CT: 1 or 2 (32 or 64 pulses per block)
   const int32_t* gate_list; // optional: only gates gate_list[i], i < *gate_count
   const int32_t* gate_count;
 };

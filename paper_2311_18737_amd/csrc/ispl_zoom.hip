@@ -96,34 +96,56 @@ __device__ __forceinline__ float2 load_sample(const void* base, int64_t i) {
   }
 }
 
-// Builds one 64-sample chunk of the B operand for this thread's column:
-// groups qg = q0 + NQ i (4 samples each), decoded, shifted to the window,
-// scaled and split into high and low halves, stored in the MFMA layout
-// (k-step qg / 2, lane half qg % 2).
-template <int PREC, int ST, int CT>
-__device__ __forceinline__ void build_chunk(const ZoomArgs& a, Frag (*bh)[ZKS][64],
-                                            Frag (*bl)[ZKS][64], int ch, int pc, int q0,
-                                            bool live, int64_t rowp, const float2* txp,
-                                            uint32_t k0, float scale) {
+// One 64-sample chunk of the B operand for this thread's column, in two
+// halves so the global loads can be in flight while the matrix cores work on
+// the previous chunk: load_chunk fetches the samples, codes and shift
+// twiddles of groups qg = q0 + NQ i (4 samples each); store_chunk decodes,
+// shifts, scales and splits them into high and low halves and stores them in
+// the MFMA layout (k-step qg / 2, lane half qg % 2).
+template <int CT>
+struct ChunkRegs {
+  float2 x[CT][4], c[CT][4], w[CT][4];
+};
+
+template <int ST, int CT>
+__device__ __forceinline__ void load_chunk(const ZoomArgs& a, ChunkRegs<CT>& r, int ch, int q0,
+                                           bool live, int64_t rowp, const float2* txp,
+                                           uint32_t k0) {
   constexpr int NQ = ZT / (32 * CT);
   const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
   const uint32_t nmask = static_cast<uint32_t>(a.n_fft - 1);
+#pragma unroll
+  for (int i = 0; i < CT; ++i)
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      const int n = ch * ZCHUNK + 4 * (q0 + NQ * i) + s2;
+      if (live && n < a.code_len) {
+        r.x[i][s2] = load_sample<ST>(a.samples, rowp + n);
+        r.c[i][s2] = txp[n];
+        // N is a power of two, so k0 n mod N survives the 32-bit wrap
+        r.w[i][s2] = tw[(k0 * static_cast<uint32_t>(n)) & nmask];
+      } else {
+        r.x[i][s2] = make_float2(0.f, 0.f);
+        r.c[i][s2] = make_float2(0.f, 0.f);
+        r.w[i][s2] = make_float2(0.f, 0.f);
+      }
+    }
+}
+
+template <int PREC, int CT>
+__device__ __forceinline__ void store_chunk(const ChunkRegs<CT>& r, Frag (*bh)[ZKS][64],
+                                            Frag (*bl)[ZKS][64], int pc, int q0, float scale) {
+  constexpr int NQ = ZT / (32 * CT);
 #pragma unroll
   for (int i = 0; i < CT; ++i) {
     const int qg = q0 + NQ * i;
     Frag fh, fl;
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
-      const int n = ch * ZCHUNK + 4 * qg + s2;
-      float2 y = make_float2(0.f, 0.f);
-      if (live && n < a.code_len) {
-        const float2 x = load_sample<ST>(a.samples, rowp + n);
-        const float2 c = txp[n];
-        const float2 d = make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
-        // N is a power of two, so k0 n mod N survives the 32-bit wrap
-        const float2 w = tw[(k0 * static_cast<uint32_t>(n)) & nmask];
-        y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * scale, fmaf(d.x, w.y, d.y * w.x) * scale);
-      }
+      const float2 x = r.x[i][s2], c = r.c[i][s2], w = r.w[i][s2];
+      const float2 d = make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
+      const float2 y =
+          make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * scale, fmaf(d.x, w.y, d.y * w.x) * scale);
       uint32_t rh, rl, ih, il;
       split2<PREC>(y.x, rh, rl);
       split2<PREC>(y.y, ih, il);
@@ -138,10 +160,10 @@ __device__ __forceinline__ void build_chunk(const ZoomArgs& a, Frag (*bh)[ZKS][6
 
 // RT: 32-row MFMA tiles per wave (16 bins each); CT: 32-pulse column tiles per
 // pulse block.  A workgroup owns one gate, 128 RT bins and one chunk of the
-// pulses.  The B chunks are double-buffered in LDS (the next chunk is built
-// while the current one feeds the matrix cores, one barrier per chunk) and
-// the A fragments of the next k-step are loaded while the current ones are
-// multiplied.
+// pulses.  The B chunks are double-buffered in LDS: the next chunk's samples
+// are fetched before the current chunk's matrix work and stored after it (one
+// barrier per chunk), and the A fragments of the next k-step are loaded while
+// the current ones are multiplied.
 template <int PREC, int ST, int RT, int CT>
 __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
   constexpr int NCOL = 32 * CT;
@@ -205,7 +227,9 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[r][ct][i] = 0.f;
 
-    build_chunk<PREC, ST, CT>(a, bh[0], bl[0], 0, pc, q0, live, rowp, txp, k0, scale);
+    ChunkRegs<CT> cr;
+    load_chunk<ST, CT>(a, cr, 0, q0, live, rowp, txp, k0);
+    store_chunk<PREC, CT>(cr, bh[0], bl[0], pc, q0, scale);
     Frag nh[RT], nl[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) {
@@ -215,9 +239,8 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
     __syncthreads();
     for (int ch = 0; ch < nchunks; ++ch) {
       const int b = ch & 1;
-      if (ch + 1 < nchunks)
-        build_chunk<PREC, ST, CT>(a, bh[b ^ 1], bl[b ^ 1], ch + 1, pc, q0, live, rowp, txp, k0,
-                                  scale);
+      const bool more = ch + 1 < nchunks;
+      if (more) load_chunk<ST, CT>(a, cr, ch + 1, q0, live, rowp, txp, k0);  // in flight below
 #pragma unroll
       for (int ks = 0; ks < ZKS; ++ks) {
         Frag fh[RT], fl[RT];
@@ -245,6 +268,7 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
           }
         }
       }
+      if (more) store_chunk<PREC, CT>(cr, bh[b ^ 1], bl[b ^ 1], pc, q0, scale);
       __syncthreads();
     }
 
@@ -350,21 +374,12 @@ template <int PREC, int ST, int RT>
 hipError_t launch_zoom_rt(const ZoomArgs& a, int ct, hipStream_t stream) {
   const unsigned blocks =
       static_cast<unsigned>(a.n_gates) * (a.n_bins / (128 * RT)) * static_cast<unsigned>(a.chunks);
-  switch (ct) {
-    case 1:
-      hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 1>), dim3(blocks), dim3(ZT), 0, stream, a);
-      break;
-    case 2:
-      hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 2>), dim3(blocks), dim3(ZT), 0, stream, a);
-      break;
-    default:
-      if constexpr (RT == 1) {
-        hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 4>), dim3(blocks), dim3(ZT), 0, stream, a);
-      } else {
-        return hipErrorInvalidValue;  // 2 x 4 accumulator tiles would spill
-      }
-      break;
-  }
+  if (ct == 1)
+    hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 1>), dim3(blocks), dim3(ZT), 0, stream, a);
+  else if (ct == 2)
+    hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 2>), dim3(blocks), dim3(ZT), 0, stream, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
