@@ -21,7 +21,7 @@
 //
 // Tiling: a workgroup of 8 waves owns one gate, 128 or 256 bins (one or two
 // 32-row MFMA tiles per wave) and a chunk of the pulses, which it sweeps in
-// blocks of 32, 64 or 128 columns (32x32 tiles).  The decoded, shifted and
+// blocks of 32 or 64 columns (one or two 32x32 tiles).  The decoded, shifted and
 // split samples of a block are built per 64-sample chunk in LDS in the MFMA
 // B-operand layout, double-buffered so that building overlaps the matrix
 // work; the A operand (DFT matrix, split) streams from a table laid out in
