@@ -96,56 +96,70 @@ __device__ __forceinline__ float2 load_sample(const void* base, int64_t i) {
   }
 }
 
-// One 64-sample chunk of the B operand for this thread's column, in two
-// halves so the global loads can be in flight while the matrix cores work on
-// the previous chunk: load_chunk fetches the samples, codes and shift
-// twiddles of groups qg = q0 + NQ i (4 samples each); store_chunk decodes,
-// shifts, scales and splits them into high and low halves and stores them in
-// the MFMA layout (k-step qg / 2, lane half qg % 2).
+// One 64-sample chunk of the B operand.  A thread builds items (column pc,
+// group qg of 4 consecutive samples) with qg = tid % 16 fixed and pc = tid / 16
+// + (ZT / 16) i, so the 16 lanes of one column read one contiguous run of the
+// pulse row (and of its code).  load_chunk fetches the samples, codes and shift
+// twiddles and can be in flight while the matrix cores work on the previous
+// chunk; every load is unconditional (indices clamped into the row), so the
+// compiler's memory counters wait for exactly the loads a use needs.
+// store_chunk zeroes samples past L and pulses past the chunk, decodes, shifts,
+// scales and splits them into high and low halves and stores them in the MFMA
+// B layout (k-step qg / 2, lane half qg % 2).
 template <int CT>
 struct ChunkRegs {
   float2 x[CT][4], c[CT][4], w[CT][4];
 };
 
+// Column pc's B fragment of k-step ks sits at slot lane ^ swz(ks, lane) of the
+// k-step's 64 slots: a bijection that keeps the matrix reads conflict-free and
+// spreads the 16 lanes of one column's store over 16 bank groups.
+__device__ __forceinline__ int b_slot(int ks, int ln) { return ln ^ ((2 * ks + (ln >> 5)) & 15); }
+
+struct ItemCtx {
+  int64_t rowp;        // sample index of the gate window in this item's pulse row
+  const float2* txp;   // code row of this item's pulse
+  bool live;           // pulse inside the chunk
+};
+
 template <int ST, int CT>
-__device__ __forceinline__ void load_chunk(const ZoomArgs& a, ChunkRegs<CT>& r, int ch, int q0,
-                                           bool live, int64_t rowp, const float2* txp,
-                                           uint32_t k0) {
-  constexpr int NQ = ZT / (32 * CT);
+__device__ __forceinline__ void load_chunk(const ZoomArgs& a, ChunkRegs<CT>& r, int ch, int qg,
+                                           const ItemCtx (&it)[CT], uint32_t k0) {
   const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
   const uint32_t nmask = static_cast<uint32_t>(a.n_fft - 1);
+  const int L = a.code_len;
 #pragma unroll
   for (int i = 0; i < CT; ++i)
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
-      const int n = ch * ZCHUNK + 4 * (q0 + NQ * i) + s2;
-      if (live && n < a.code_len) {
-        r.x[i][s2] = load_sample<ST>(a.samples, rowp + n);
-        r.c[i][s2] = txp[n];
-        // N is a power of two, so k0 n mod N survives the 32-bit wrap
-        r.w[i][s2] = tw[(k0 * static_cast<uint32_t>(n)) & nmask];
-      } else {
-        r.x[i][s2] = make_float2(0.f, 0.f);
-        r.c[i][s2] = make_float2(0.f, 0.f);
-        r.w[i][s2] = make_float2(0.f, 0.f);
-      }
+      const int n = ch * ZCHUNK + 4 * qg + s2;
+      const int ne = n < L ? n : L - 1;  // always inside the row
+      r.x[i][s2] = load_sample<ST>(a.samples, it[i].rowp + ne);
+      r.c[i][s2] = it[i].txp[ne];
+      // N is a power of two, so k0 n mod N survives the 32-bit wrap
+      r.w[i][s2] = tw[(k0 * static_cast<uint32_t>(ne)) & nmask];
     }
 }
 
 template <int PREC, int CT>
 __device__ __forceinline__ void store_chunk(const ChunkRegs<CT>& r, Frag (*bh)[ZKS][64],
-                                            Frag (*bl)[ZKS][64], int pc, int q0, float scale) {
-  constexpr int NQ = ZT / (32 * CT);
+                                            Frag (*bl)[ZKS][64], int pc0, int qg,
+                                            const float (&scale)[CT], const ItemCtx (&it)[CT],
+                                            int ch, int L) {
 #pragma unroll
   for (int i = 0; i < CT; ++i) {
-    const int qg = q0 + NQ * i;
+    const int pc = pc0 + (ZT / 16) * i;
     Frag fh, fl;
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
-      const float2 x = r.x[i][s2], c = r.c[i][s2], w = r.w[i][s2];
+      // samples past L and pulses past the chunk contribute zero
+      const bool keep = it[i].live && ch * ZCHUNK + 4 * qg + s2 < L;
+      const float2 x = keep ? r.x[i][s2] : make_float2(0.f, 0.f);
+      const float2 c = keep ? r.c[i][s2] : make_float2(0.f, 0.f);
+      const float2 w = r.w[i][s2];
       const float2 d = make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
-      const float2 y =
-          make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * scale, fmaf(d.x, w.y, d.y * w.x) * scale);
+      const float2 y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * scale[i],
+                                   fmaf(d.x, w.y, d.y * w.x) * scale[i]);
       uint32_t rh, rl, ih, il;
       split2<PREC>(y.x, rh, rl);
       split2<PREC>(y.y, ih, il);
@@ -153,9 +167,18 @@ __device__ __forceinline__ void store_chunk(const ChunkRegs<CT>& r, Frag (*bh)[Z
       fl.w[s2] = rl | (il << 16);
     }
     const int ks = qg >> 1, ln = (pc & 31) + 32 * (qg & 1), ct = pc >> 5;
-    bh[ct][ks][ln] = fh;
-    bl[ct][ks][ln] = fl;
+    bh[ct][ks][b_slot(ks, ln)] = fh;
+    bl[ct][ks][b_slot(ks, ln)] = fl;
   }
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin; renumber the first nblk of
+// them so that each XCD runs a contiguous range of work items (neighbouring
+// gates, whose sample windows overlap, then share that XCD's L2).
+__device__ __forceinline__ int zoom_xcd_id(int b, int nblk) {
+  const int xcd = b & 7, slot = b >> 3;
+  const int per = nblk >> 3, extra = nblk & 7;
+  return xcd < extra ? xcd * (per + 1) + slot : extra * (per + 1) + (xcd - extra) * per + slot;
 }
 
 // RT: 32-row MFMA tiles per wave (16 bins each); CT: 32-pulse column tiles per
@@ -174,13 +197,21 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int btiles = a.n_bins / (128 * RT);
-  int bid = blockIdx.x;
+  const int per_gate = btiles * a.chunks;
+  // With a gate list only the first count * per_gate workgroups have work;
+  // those are renumbered among themselves (uniform, before any barrier).
+  int nblk = static_cast<int>(gridDim.x);
+  if (a.gate_list) {
+    const int cnt = min(max(*a.gate_count, 0), nblk / per_gate);
+    nblk = cnt * per_gate;
+    if (static_cast<int>(blockIdx.x) >= nblk) return;
+  }
+  int bid = zoom_xcd_id(static_cast<int>(blockIdx.x), nblk);
   const int chunk = bid % a.chunks;
   bid /= a.chunks;
   const int bt = bid % btiles;
   int g = bid / btiles;
-  if (a.gate_list) {  // uniform over the workgroup, before any barrier
-    if (g >= *a.gate_count) return;
+  if (a.gate_list) {
     g = a.gate_list[g];
     if (g < 0 || g >= a.n_gates) return;
   }
@@ -209,15 +240,38 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) total[r][i] = 0.f;
 
-  // B-building role: column pc of the block, group rows q0, q0 + NQ, ...
-  const int pc = tid % NCOL, q0 = tid / NCOL;
+  // B-building role: sample group qg of columns pc0 + (ZT / 16) i
+  const int qg = tid & 15, pc0 = tid >> 4;
+  static_assert(ZT / 16 * CT == NCOL, "one item per thread and column tile");
+
+  // A fragments are fetched AD k-steps ahead into a ring (slot ks % AD, which
+  // AD | ZKS makes static).  The refill after the last k-step of a pulse
+  // block wraps to the first ones, which the next block uses.
+  constexpr int AD = 2;
+  static_assert(ZKS % AD == 0, "static ring slots");
+  Frag ah[AD][RT], al[AD][RT];
+#pragma unroll
+  for (int d = 0; d < AD; ++d)
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const int kk = d < n_ks ? d : n_ks - 1;
+      ah[d][r] = ah_t[r][static_cast<int64_t>(kk) * 64];
+      al[d][r] = al_t[r][static_cast<int64_t>(kk) * 64];
+    }
 
   for (int pb = p0; pb < p1; pb += NCOL) {
-    const int p = pb + pc;
-    const bool live = p < p1;
-    const int64_t rowp = static_cast<int64_t>(live ? p : p0) * a.stride + gate_off;
-    const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(live ? p : p0) * L : 0);
-    const float scale = (PREC == 1 && live) ? ldexpf(1.f, a.col_exp[p]) : 1.f;
+    ItemCtx it[CT];
+    float scale[CT];
+#pragma unroll
+    for (int i = 0; i < CT; ++i) {
+      const int p = pb + pc0 + (ZT / 16) * i;
+      const bool live = p < p1;
+      const int pr = live ? p : p0;
+      it[i].rowp = static_cast<int64_t>(pr) * a.stride + gate_off;
+      it[i].txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(pr) * L : 0);
+      it[i].live = live;
+      scale[i] = (PREC == 1 && live) ? ldexpf(1.f, a.col_exp[p]) : 1.f;
+    }
 
     f32x16 acc[RT][CT];
 #pragma unroll
@@ -228,47 +282,40 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
         for (int i = 0; i < 16; ++i) acc[r][ct][i] = 0.f;
 
     ChunkRegs<CT> cr;
-    load_chunk<ST, CT>(a, cr, 0, q0, live, rowp, txp, k0);
-    store_chunk<PREC, CT>(cr, bh[0], bl[0], pc, q0, scale);
-    Frag nh[RT], nl[RT];
-#pragma unroll
-    for (int r = 0; r < RT; ++r) {
-      nh[r] = ah_t[r][0];
-      nl[r] = al_t[r][0];
-    }
+    load_chunk<ST, CT>(a, cr, 0, qg, it, k0);
+    store_chunk<PREC, CT>(cr, bh[0], bl[0], pc0, qg, scale, it, 0, L);
     __syncthreads();
     for (int ch = 0; ch < nchunks; ++ch) {
       const int b = ch & 1;
       const bool more = ch + 1 < nchunks;
-      if (more) load_chunk<ST, CT>(a, cr, ch + 1, q0, live, rowp, txp, k0);  // in flight below
+      // in flight below; the last chunk re-reads itself instead of branching,
+      // so no later wait has to cover a path without these loads
+      load_chunk<ST, CT>(a, cr, more ? ch + 1 : ch, qg, it, k0);
 #pragma unroll
       for (int ks = 0; ks < ZKS; ++ks) {
-        Frag fh[RT], fl[RT];
-#pragma unroll
-        for (int r = 0; r < RT; ++r) {
-          fh[r] = nh[r];
-          fl[r] = nl[r];
-        }
-        const int nx = ch * ZKS + ks + 1;
-        if (nx < n_ks) {
-#pragma unroll
-          for (int r = 0; r < RT; ++r) {
-            nh[r] = ah_t[r][static_cast<int64_t>(nx) * 64];
-            nl[r] = al_t[r][static_cast<int64_t>(nx) * 64];
-          }
-        }
+        const int slot = ks % AD;
 #pragma unroll
         for (int ct = 0; ct < CT; ++ct) {
-          const Frag fbh = bh[b][ct][ks][lane], fbl = bl[b][ct][ks][lane];
+          const Frag fbh = bh[b][ct][ks][b_slot(ks, lane)], fbl = bl[b][ct][ks][b_slot(ks, lane)];
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
-            acc[r][ct] = mfma<PREC>(fh[r], fbh, acc[r][ct]);
-            acc[r][ct] = mfma<PREC>(fh[r], fbl, acc[r][ct]);
-            acc[r][ct] = mfma<PREC>(fl[r], fbh, acc[r][ct]);
+            acc[r][ct] = mfma<PREC>(ah[slot][r], fbh, acc[r][ct]);
+            acc[r][ct] = mfma<PREC>(ah[slot][r], fbl, acc[r][ct]);
+            acc[r][ct] = mfma<PREC>(al[slot][r], fbh, acc[r][ct]);
           }
         }
+        // refill the slot with k-step kk + AD, wrapping into the next block
+        int kn = ch * ZKS + ks + AD;
+        if (kn >= n_ks) kn -= n_ks;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          ah[slot][r] = ah_t[r][static_cast<int64_t>(kn) * 64];
+          al[slot][r] = al_t[r][static_cast<int64_t>(kn) * 64];
+        }
       }
-      if (more) store_chunk<PREC, CT>(cr, bh[b ^ 1], bl[b ^ 1], pc, q0, scale);
+      // unconditional too (after the last chunk it fills the idle buffer), so
+      // the compiler keeps the loads above the matrix work
+      store_chunk<PREC, CT>(cr, bh[b ^ 1], bl[b ^ 1], pc0, qg, scale, it, more ? ch + 1 : ch, L);
       __syncthreads();
     }
 
