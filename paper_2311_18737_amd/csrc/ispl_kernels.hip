@@ -379,13 +379,16 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   float2* xw = xs + wave * XWAVE;
   if constexpr (RW == 1) {
     // One wave owns the gate: thread tid loads samples tid + 64 i, which are
-    // exactly its pass-1 inputs, so the row needs no LDS stage and no barrier;
-    // the other waves on the SIMD hide the load latency.
+    // exactly its pass-1 inputs, so the row needs no LDS stage and no barrier.
+    // The next pulse's samples and codes are fetched before this pulse's
+    // transform, so a wave that is alone on its SIMD (few gates, short pulse
+    // chunks) does not wait for memory once per pulse.
+    if (p0 < p1) load(p0);
     for (int p = p0; p < p1; ++p) {
-      load(p);
       float2 v[16];
 #pragma unroll
       for (int j = 0; j < 16; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
+      if (p + 1 < p1) load(p + 1);
       wave_fft_accumulate(v, xw, wt, dk, acc, lane);
     }
   } else {
@@ -570,14 +573,26 @@ peak_pick(const float* __restrict__ spectra, int32_t n_gates, int32_t n_fft, int
   const int len = lo < hi ? hi - lo : (n_fft - lo) + hi;
   float bv = -INFINITY;
   int bk = INT_MAX;
-  for (int i = threadIdx.x; i < len; i += blockDim.x) {
-    int k = lo + i;
-    if (k >= n_fft) k -= n_fft;
-    const float v = row[k];
-    if (peak_better(v, k, bv, bk)) {
-      bv = v;
-      bk = k;
+  // PEAK_UNROLL loads in flight per thread before any comparison; the
+  // (value, -bin) order is total, so the visiting order does not matter.
+  constexpr int PEAK_UNROLL = 16;
+  for (int i0 = threadIdx.x; i0 < len; i0 += PEAK_UNROLL * blockDim.x) {
+    float v[PEAK_UNROLL];
+    int k[PEAK_UNROLL];
+#pragma unroll
+    for (int u = 0; u < PEAK_UNROLL; ++u) {
+      const int i = i0 + u * static_cast<int>(blockDim.x);
+      k[u] = lo + i;
+      if (k[u] >= n_fft) k[u] -= n_fft;
+      v[u] = i < len ? row[k[u]] : -INFINITY;
+      if (i >= len) k[u] = INT_MAX;  // never better than anything
     }
+#pragma unroll
+    for (int u = 0; u < PEAK_UNROLL; ++u)
+      if (peak_better(v[u], k[u], bv, bk)) {
+        bv = v[u];
+        bk = k[u];
+      }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
