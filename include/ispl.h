@@ -327,7 +327,7 @@ void ispl_destroy(ispl_ctx* ctx);
  * so light and heavy modes share the chip without host launches between them.
  * Each mode computes exactly what ispl_integrate_spectra computes for it; the
  * plan of each mode (waves per workgroup, pulse chunks) and the graph's shape
- * come from the project's autotuner.
+ * come from the automatic plan, a hand-set plan or the project's autotuner.
  *   ispl_batch_create   1 <= n_modes <= 8 configs (as for ispl_create).
  *   ispl_batch_io       per mode: samples, tx_code, tx_per_pulse, n_pulses,
  *                       spectra, with the meanings of ispl_integrate_spectra.
@@ -343,7 +343,12 @@ void ispl_destroy(ispl_ctx* ctx);
  *                       candidate is the graph's median time over `trials`
  *                       runs on an internal stream.  Keeps and returns the
  *                       fastest plan and its time (either pointer may be
- *                       NULL).  It writes the spectra of io.
+ *                       NULL).  It writes the spectra of io.  Builds
+ *                       without ISPL_BATCH_TUNER defined (the default) return
+ *                       ISPL_ERR_UNSUPPORTED after the argument checks: the
+ *                       tuner is switched off until a host-side crash seen
+ *                       while it ran is explained; set_plan still applies
+ *                       hand-chosen plans.
  *   ispl_batch_get_plan / set_plan  the plan in use (waves 0 and chunks 0 mean
  *                       the automatic choice; waves only for modes with
  *                       L <= 1024: a power of two <= min(16, N/1024)).

@@ -650,7 +650,8 @@ class Batch:
 
     def tune(self, inputs, outs=None, trials: int = 3):
         """Autotune the plan on these inputs (writes their spectra); returns
-        (plan dict, best ms)."""
+        (plan dict, best ms).  Raises IsplError (ISPL_ERR_UNSUPPORTED) in
+        builds where the library's autotuner is switched off."""
         io, _ = self._io(inputs, outs)
         plan = _lib.IsplBatchPlan()
         ms = ctypes.c_float()

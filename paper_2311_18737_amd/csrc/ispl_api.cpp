@@ -1172,6 +1172,9 @@ ispl_status batch_run(ispl_batch* b, const ispl_batch_io* io, int32_t accumulate
 // Captures every mode's launches: on parallel branches (fork / join events)
 // or one after another in plan order, then instantiates the graph.
 ispl_status batch_capture(ispl_batch* b, const ispl_batch_io* io, int32_t accumulate) {
+  // until a new graph is instantiated there is none to replay, also after a
+  // failed capture
+  b->graph_valid = false;
   if (b->exec) {
     (void)hipGraphExecDestroy(b->exec);
     b->exec = nullptr;
@@ -1331,6 +1334,13 @@ ispl_status ispl_batch_tune(ispl_batch* b, const ispl_batch_io* io, int32_t tria
   if (!b || !io) return fail(ISPL_ERR_INVALID_ARG, "batch or io is NULL");
   if (trials < 1 || trials > 100)
     return fail(ISPL_ERR_INVALID_ARG, "trials %d outside [1, 100]", trials);
+#ifndef ISPL_BATCH_TUNER
+  // Switched off: a process running the tuner ended in a host-side crash whose
+  // cause is not known yet.  Plans can still be set by hand (ispl_batch_set_plan).
+  (void)best;
+  (void)best_ms;
+  return fail(ISPL_ERR_UNSUPPORTED, "the batch autotuner is switched off in this build");
+#else
   DeviceGuard guard(b->device);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
@@ -1425,6 +1435,7 @@ ispl_status ispl_batch_tune(ispl_batch* b, const ispl_batch_io* io, int32_t tria
   if (best) *best = cur;
   if (best_ms) *best_ms = cur_ms;
   return ok();
+#endif
 }
 
 }  // extern "C"

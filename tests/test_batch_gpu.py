@@ -99,7 +99,10 @@ def test_batch_equals_each_mode_bit_for_bit(ispl, st):
     b.close()
 
 
-def test_autotuner_and_plans(ispl):
+@pytest.mark.skip(reason="the library's batch autotuner is switched off: a process running it "
+                         "(this test) ended in a host-side segmentation fault whose cause is not "
+                         "found yet; it stays off the GPU until it is")
+def test_autotuner(ispl):
     geo, data = make(MODES, seed=5)
     inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
     ref = per_mode(ispl, geo, data, "c64")
@@ -113,6 +116,24 @@ def test_autotuner_and_plans(ispl):
     for o, r in zip(outs, ref):
         scale = torch.maximum(r, r.mean(dim=1, keepdim=True))
         assert float(((o - r).abs() / torch.clamp(scale, min=1e-30)).max()) <= 2e-6
+    b.close()
+
+
+def test_autotuner_reports_switched_off(ispl):
+    geo, data = make(MODES[:2], seed=6)
+    inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
+    b = ispl.Batch(geo)
+    with pytest.raises(ispl.IsplError) as err:
+        b.tune(inputs, trials=2)
+    assert err.value.status == ispl.ISPL_ERR_UNSUPPORTED
+    b.close()
+
+
+def test_hand_set_plans(ispl):
+    geo, data = make(MODES, seed=5)
+    inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
+    ref = per_mode(ispl, geo, data, "c64")
+    b = ispl.Batch(geo)
     # other tile shapes (waves per workgroup) and serial branches: bit for bit
     for waves, serial in (([2, 4, 8, 0], False), ([1, 1, 2, 0], True), ([4, 8, 16, 0], False)):
         b.set_plan(order=[3, 2, 1, 0], waves=waves, serial=serial)
@@ -156,4 +177,36 @@ def test_batch_mixed_sample_types(ispl):
     torch.cuda.synchronize()
     for o, r in zip(outs, ref):
         assert torch.equal(o, r)
+    b.close()
+
+
+def test_tile_shape_beyond_scratch_and_an_error_inside_capture(ispl):
+    """A tuned tile shape whose plan wants more pulse chunks than the context's
+    scratch holds (one wave per workgroup on 200 gates x 500 pulses asks for 11,
+    the scratch holds 8) runs with the scratch's count; a mode whose call fails
+    inside the graph capture rejoins its branch, the call reports the error and
+    the batch stays usable.  Regression test for the tuner's candidate shapes on
+    the uneven-batch workload."""
+    modes = [(128, 4096, 200, 500), (480, 8192, 5, 12)]
+    geo, data = make(modes, seed=11)
+    inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
+    ref = per_mode(ispl, geo, data, "c64")
+    b = ispl.Batch(geo)
+    b.set_plan(waves=[1, 0])
+    say("  shape beyond the scratch")
+    outs = b.integrate(inputs)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):  # same chunk count as the automatic plan: bit for bit
+        assert torch.equal(o, r)
+    say("  error inside the capture")
+    xs, xt = inputs[1]
+    bad = [inputs[0], (torch.cat([xs, xs]), torch.cat([xt, xt]))]  # 24 pulses > max_pulses 12
+    with pytest.raises(ispl.IsplError):
+        b.integrate(bad)
+    for use_graph in (True, False):
+        outs = [torch.full_like(r, -1.0) for r in ref]
+        b.integrate(inputs, outs, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for o, r in zip(outs, ref):
+            assert torch.equal(o, r), use_graph
     b.close()
