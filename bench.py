@@ -475,10 +475,8 @@ def main():
                     help="timed runs of the paper's Section 4 workload (0 = skip)")
     ap.add_argument("--zoom-steps", type=int, default=10,
                     help="timed runs of the matrix-core zoom DFT study (0 = skip)")
-    ap.add_argument("--batch-steps", type=int, default=0,
-                    help="timed runs of the uneven-batch study at full size (0 = skip; off by "
-                         "default: its first full-size run ended in a host-side crash whose "
-                         "cause is not found yet)")
+    ap.add_argument("--batch-steps", type=int, default=5,
+                    help="timed runs of the uneven-batch study at full size (0 = skip)")
     ap.add_argument("--stream-reps", type=int, default=3,
                     help="timed runs from pinned host memory (streaming ingest; 0 = skip)")
     ap.add_argument("--lzoom-steps", type=int, default=20,
