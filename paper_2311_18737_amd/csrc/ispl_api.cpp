@@ -26,6 +26,7 @@ struct ispl_ctx {
   float* partial;       // chunks_max * G * N floats (nullptr when chunks_max == 1)
   int32_t force_rw;     // tuned plan (0: automatic): waves per workgroup, L <= 1024 only
   int32_t force_chunks; // tuned plan (0: automatic): pulse chunks, <= chunks_max
+  int32_t min_chunk_pulses;  // fewest pulses per chunk of an automatic plan
 };
 
 namespace {
@@ -101,7 +102,7 @@ struct Plan {
 };
 
 Plan make_plan(const ispl_config& c, int32_t n_pulses, int32_t force_rw = 0,
-               int32_t force_chunks = 0) {
+               int32_t force_chunks = 0, int32_t min_chunk_pulses = kMinChunkPulses) {
   Plan pl{};
   pl.sub_len = c.code_len <= ispl::SUB ? ispl::SUB : 16 * ispl::SUB;
   pl.r = c.fft_len / pl.sub_len;
@@ -122,7 +123,7 @@ Plan make_plan(const ispl_config& c, int32_t n_pulses, int32_t force_rw = 0,
   // pulses per chunk (a chunk's partial spectrum costs a write and a read)
   int64_t chunks = 1;
   if (base < 2 * slots) chunks = (2 * slots + base - 1) / base;
-  const int64_t by_pulses = n_pulses / kMinChunkPulses;
+  const int64_t by_pulses = n_pulses / min_chunk_pulses;
   if (chunks > by_pulses) chunks = by_pulses;
   if (chunks > kMaxChunks) chunks = kMaxChunks;
   const int64_t gn_bytes = static_cast<int64_t>(c.n_gates) * c.fft_len * 4;
@@ -344,7 +345,9 @@ ispl_status ispl_plan(const ispl_config* cfg, int32_t n_pulses, int32_t* chunks,
   return ok();
 }
 
-ispl_status ispl_create(const ispl_config* cfg, ispl_ctx** out) {
+// A context whose automatic plans keep at least min_chunk_pulses pulses per
+// chunk (ispl_create: kMinChunkPulses).
+static ispl_status create_ctx(const ispl_config* cfg, int32_t min_chunk_pulses, ispl_ctx** out) {
   if (!out) return fail(ISPL_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   ispl_status st = validate_config(cfg);
@@ -367,7 +370,8 @@ ispl_status ispl_create(const ispl_config* cfg, ispl_ctx** out) {
   ispl_ctx* ctx = new (std::nothrow) ispl_ctx{};
   if (!ctx) return fail(ISPL_ERR_OUT_OF_MEMORY, "host allocation");
   ctx->cfg = *cfg;
-  const Plan worst = make_plan(*cfg, cfg->max_pulses);
+  ctx->min_chunk_pulses = min_chunk_pulses;
+  const Plan worst = make_plan(*cfg, cfg->max_pulses, 0, 0, min_chunk_pulses);
 
   const std::vector<float> tw = twiddle_table(cfg->fft_len);
   e = hipMalloc(reinterpret_cast<void**>(&ctx->twiddle), tw.size() * sizeof(float));
@@ -399,6 +403,10 @@ ispl_status ispl_create(const ispl_config* cfg, ispl_ctx** out) {
   return ok();
 }
 
+ispl_status ispl_create(const ispl_config* cfg, ispl_ctx** out) {
+  return create_ctx(cfg, kMinChunkPulses, out);
+}
+
 void ispl_destroy(ispl_ctx* ctx) {
   if (!ctx) return;
   {
@@ -410,10 +418,15 @@ void ispl_destroy(ispl_ctx* ctx) {
   delete ctx;
 }
 
+// With deferred_chunks non-NULL a pulse-chunked plan leaves its partial
+// spectra in the context's scratch ([C][G][N]) instead of reducing them into
+// `spectra`; *deferred_chunks reports C (1: `spectra` holds the result).
 static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const float* tx_code,
                                   int32_t tx_per_pulse, int32_t n_pulses,
                                   const int32_t* gate_list, const int32_t* gate_count,
-                                  float* spectra, int32_t accumulate, void* stream) {
+                                  float* spectra, int32_t accumulate, void* stream,
+                                  int32_t* deferred_chunks = nullptr) {
+  if (deferred_chunks) *deferred_chunks = 1;
   if (!ctx) return fail(ISPL_ERR_INVALID_ARG, "context is NULL");
   const ispl_config& c = ctx->cfg;
   if (n_pulses < 0 || n_pulses > c.max_pulses)
@@ -445,7 +458,7 @@ static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const floa
     }
     return ok();
   }
-  Plan pl = make_plan(c, n_pulses, ctx->force_rw, ctx->force_chunks);
+  Plan pl = make_plan(c, n_pulses, ctx->force_rw, ctx->force_chunks, ctx->min_chunk_pulses);
   // a tuned tile shape can ask for more chunks than the scratch was sized for;
   // fewer chunks only change how the pulses are split
   if (pl.chunks > ctx->chunks_max) pl.chunks = ctx->chunks_max;
@@ -474,6 +487,10 @@ static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const floa
   e = ispl::launch_fused(a, s);
   if (e != hipSuccess) return hip_fail(e, "fused launch");
   if (pl.chunks > 1) {
+    if (deferred_chunks && !accumulate) {
+      *deferred_chunks = pl.chunks;
+      return ok();
+    }
     e = ispl::launch_reduce_chunks(ctx->partial, spectra, elems, pl.chunks, accumulate,
                                    c.fft_len, gate_list, gate_count, s);
     if (e != hipSuccess) return hip_fail(e, "chunk reduce launch");
@@ -566,10 +583,15 @@ void ispl_zoom_destroy(ispl_zoom* z) {
   delete z;
 }
 
+// deferred_chunks: as for integrate_impl (partial windows [C][G][K] stay in
+// the zoom's scratch).  exponents_ready: the FP16 column exponents are already
+// in the zoom's col_exp (see launch_select_and_exponents).
 static ispl_status zoom_impl(ispl_zoom* z, const void* samples, const float* tx_code,
                              int32_t tx_per_pulse, int32_t n_pulses, const int32_t* bin_start,
                              const int32_t* gate_list, const int32_t* gate_count, float* spectra,
-                             int32_t accumulate, void* stream) {
+                             int32_t accumulate, void* stream, int32_t* deferred_chunks = nullptr,
+                             bool exponents_ready = false) {
+  if (deferred_chunks) *deferred_chunks = 1;
   if (!z) return fail(ISPL_ERR_INVALID_ARG, "zoom is NULL");
   const ispl_config& c = z->ctx->cfg;
   if (n_pulses < 0 || n_pulses > c.max_pulses)
@@ -633,8 +655,12 @@ static ispl_status zoom_impl(ispl_zoom* z, const void* samples, const float* tx_
   a.row_lo = c.first_gate;
   a.row_hi = static_cast<int64_t>(c.first_gate) + static_cast<int64_t>(c.n_gates - 1) * c.gate_step +
              c.code_len;
-  hipError_t e = ispl::launch_zoom(a, s);
+  hipError_t e = ispl::launch_zoom(a, s, !exponents_ready);
   if (e != hipSuccess) return hip_fail(e, "zoom launch");
+  if (zp.chunks > 1 && deferred_chunks && !accumulate) {
+    *deferred_chunks = zp.chunks;
+    return ok();
+  }
   if (zp.chunks > 1) {
     e = ispl::launch_reduce_chunks(z->partial, spectra, static_cast<int64_t>(c.n_gates) * z->n_bins,
                                    zp.chunks, accumulate, z->n_bins, gate_list, gate_count, s);
@@ -1004,7 +1030,9 @@ ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t win
   z->threshold = threshold;
   ispl_config cc = *cfg;
   cc.fft_len = ispl::NET_LEN;
-  st = ispl_create(&cc, &z->coarse);
+  // the coarse transforms are short: chunks of 4 pulses give enough waves to
+  // fill the chip on small workloads, and the network sums the partials
+  st = create_ctx(&cc, 4, &z->coarse);
   if (st == ISPL_OK) st = ispl_create(cfg, &z->fine);
   if (st == ISPL_OK) st = ispl_zoom_create(z->fine, window_bins, zoom_precision, &z->zoom);
   if (st != ISPL_OK) {
@@ -1069,30 +1097,49 @@ ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx
   const int32_t G = z->n_gates;
   DeviceGuard guard(c.device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  // coarse spectra of every gate (the plain path at N = 1024)
+  // coarse spectra of every gate (the plain path at N = 1024); pulse-chunk
+  // partials are summed by the network kernel, which writes coarse_spectra
+  int32_t coarse_chunks = 1, zoom_chunks = 1, fine_chunks = 1;
   ispl_status st = integrate_impl(z->coarse, samples, tx_code, tx_per_pulse, n_pulses, nullptr,
-                                  nullptr, z->coarse_spectra, 0, stream);
+                                  nullptr, z->coarse_spectra, 0, stream, &coarse_chunks);
   if (st != ISPL_OK) return st;
-  // network on the coarse spectra (features formed in the kernel), BF16 logits,
-  // windows and the two gate lists
+  // network on the coarse spectra (features formed in the kernel), BF16 logits;
+  // then windows, the two gate lists and the zoom's FP16 pulse exponents in
+  // one launch
   hipError_t e;
   bf16_table_ready(z->net, s, &e);
   if (e == hipSuccess)
     e = ispl::launch_net_forward_bf16(z->net->bf16_weights, z->coarse_spectra, G, z->logits, s,
-                                      true);
-  if (e == hipSuccess)
-    e = ispl::launch_select_windows(z->logits, G, c.fft_len, z->window_bins, z->threshold,
-                                    z->bin_start, z->confidence, z->flag, z->zoom_list,
-                                    z->fallback_list, z->counts, z->done, s);
+                                      true, z->coarse->partial, coarse_chunks, z->coarse_spectra);
+  if (e == hipSuccess) {
+    ispl::PulseExpArgs pe{};
+    const bool fp16 = z->zoom->precision == ISPL_ZOOM_FP16X3 && n_pulses > 0;
+    pe.samples = samples;
+    pe.tx = tx_code;
+    pe.exps = z->zoom->col_exp;
+    pe.stride = c.pulse_stride;
+    pe.lo = c.first_gate;
+    pe.hi = static_cast<int64_t>(c.first_gate) + static_cast<int64_t>(c.n_gates - 1) * c.gate_step +
+            c.code_len;
+    pe.sample_type = c.sample_type;
+    pe.code_len = c.code_len;
+    pe.tx_per_pulse = tx_per_pulse;
+    pe.n_pulses = fp16 ? n_pulses : 0;
+    e = ispl::launch_select_and_exponents(z->logits, G, c.fft_len, z->window_bins, z->threshold,
+                                          z->bin_start, z->confidence, z->flag, z->zoom_list,
+                                          z->fallback_list, z->counts, z->done, pe, s);
+  }
   if (e != hipSuccess) return hip_fail(e, "learned-zoom network launch");
-  // zoomed gates: K bins around the proposed centre; the others: full spectra
+  // zoomed gates: K bins around the proposed centre; the others: full spectra;
+  // chunk partials of both are summed by the peak launch
   st = zoom_impl(z->zoom, samples, tx_code, tx_per_pulse, n_pulses, z->bin_start, z->zoom_list,
-                 z->counts, z->window_spectra, 0, stream);
+                 z->counts, z->window_spectra, 0, stream, &zoom_chunks, true);
   if (st != ISPL_OK) return st;
   st = integrate_impl(z->fine, samples, tx_code, tx_per_pulse, n_pulses, z->fallback_list,
-                      z->counts + 1, z->full_spectra, 0, stream);
+                      z->counts + 1, z->full_spectra, 0, stream, &fine_chunks);
   if (st != ISPL_OK) return st;
-  e = ispl::launch_split_peaks(z->window_spectra, z->full_spectra, z->flag, z->bin_start, G,
+  e = ispl::launch_split_peaks(z->window_spectra, z->zoom->partial, zoom_chunks, z->full_spectra,
+                               z->fine->partial, fine_chunks, z->flag, z->bin_start, G,
                                z->window_bins, c.fft_len, peak_bin, peak_power, s);
   if (e != hipSuccess) return hip_fail(e, "learned-zoom peak launch");
   return ok();

@@ -475,11 +475,17 @@ __device__ __forceinline__ void mfma_layer(const uint16_t* __restrict__ src, uin
 }
 
 // FROM_SPECTRA: the input rows are coarse spectra and the features
-// log(max(S / mean S, 1e-30)) are formed here (as log_features does).
+// log(max(S / mean S, 1e-30)) are formed here (as log_features does).  With
+// chunks > 1 the spectra are still split over pulse chunks ([chunks][batch][T]
+// partials): each row is summed in ascending chunk order, as the separate
+// chunk reduction does, and written to x_out before use.
 template <bool FROM_SPECTRA>
 __global__ void __launch_bounds__(FW_THREADS) net_forward_bf16(const float* __restrict__ x,
                                                                const NetBf16* __restrict__ nw,
-                                                               float* __restrict__ logits) {
+                                                               float* __restrict__ logits,
+                                                               const float* __restrict__ partial,
+                                                               int32_t chunks,
+                                                               float* __restrict__ x_out) {
   __shared__ __attribute__((aligned(16))) float xs[T];
   __shared__ __attribute__((aligned(16))) uint16_t act0[T * 32];
   __shared__ __attribute__((aligned(16))) uint16_t act1[T * 32];
@@ -490,7 +496,28 @@ __global__ void __launch_bounds__(FW_THREADS) net_forward_bf16(const float* __re
   const int h = lane >> 5, c = lane & 31;
   if (j < 32 * TAPS) w4s[j] = nw->w4[j];
   static_assert(FW_PER_THREAD == 2, "two input values per thread");
-  float2 v = reinterpret_cast<const float2*>(x + static_cast<int64_t>(g) * T)[j];
+  float2 v;
+  if (FROM_SPECTRA && chunks > 1) {
+    const int64_t cs = static_cast<int64_t>(gridDim.x) * T;
+    const float2* pr = reinterpret_cast<const float2*>(partial + static_cast<int64_t>(g) * T) + j;
+    v = make_float2(0.f, 0.f);
+    // eight loads in flight, then the sums in ascending chunk order
+    for (int c0 = 0; c0 < chunks; c0 += 8) {
+      float2 q[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        q[u] = c0 + u < chunks ? pr[(c0 + u) * (cs / 2)] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (c0 + u < chunks) {
+          v.x += q[u].x;
+          v.y += q[u].y;
+        }
+    }
+    reinterpret_cast<float2*>(x_out + static_cast<int64_t>(g) * T)[j] = v;
+  } else {
+    v = reinterpret_cast<const float2*>(x + static_cast<int64_t>(g) * T)[j];
+  }
   if (FROM_SPECTRA) {
     float sum = v.x + v.y;
 #pragma unroll
@@ -575,13 +602,14 @@ hipError_t launch_net_prep_bf16(const float* params, void* table, hipStream_t s)
 }
 
 hipError_t launch_net_forward_bf16(const void* table, const float* x, int batch, float* logits,
-                                   hipStream_t s, bool from_spectra) {
+                                   hipStream_t s, bool from_spectra, const float* partial,
+                                   int32_t chunks, float* x_out) {
   if (from_spectra)
     hipLaunchKernelGGL(net_forward_bf16<true>, dim3(batch), dim3(FW_THREADS), 0, s, x,
-                       static_cast<const NetBf16*>(table), logits);
+                       static_cast<const NetBf16*>(table), logits, partial, chunks, x_out);
   else
     hipLaunchKernelGGL(net_forward_bf16<false>, dim3(batch), dim3(FW_THREADS), 0, s, x,
-                       static_cast<const NetBf16*>(table), logits);
+                       static_cast<const NetBf16*>(table), logits, nullptr, 1, nullptr);
   return hipGetLastError();
 }
 

@@ -1,0 +1,70 @@
+// Device helpers shared by several kernel files (HIP only; never included by
+// host-only translation units).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+namespace ispl {
+
+// Sample i of a row: complex64, or an int16 (re, im) pair (exact in float).
+__device__ __forceinline__ float2 load_any_sample(const void* base, int32_t sample_type,
+                                                  int64_t i) {
+  if (sample_type == 1) {
+    const uint32_t r = reinterpret_cast<const uint32_t*>(base)[i];
+    return make_float2(static_cast<float>(static_cast<int16_t>(r & 0xffffu)),
+                       static_cast<float>(static_cast<int32_t>(r) >> 16));
+  }
+  return reinterpret_cast<const float2*>(base)[i];
+}
+
+// FP16 column exponent of pulse p, computed by one workgroup of 256 threads:
+// the e with max|x| max|c| 2^e < 2^14 over the samples [lo, hi) of the pulse
+// row that some gate reads and over the pulse's code, so that no split FP16
+// value of the zoom DFT overflows and the low halves stay normal down to about
+// 2^-17 of that maximum.  Clamped to [-60, 60]; 0 for an all-zero pulse.
+__device__ __forceinline__ void pulse_exponent_block(const void* __restrict__ samples,
+                                                     int32_t sample_type,
+                                                     const float* __restrict__ tx,
+                                                     int64_t stride, int64_t lo, int64_t hi,
+                                                     int32_t code_len, int32_t tx_per_pulse,
+                                                     int p, int32_t* __restrict__ exps) {
+  __shared__ float red[2][4];
+  float mx = 0.f, mc = 0.f;
+  const int64_t base = static_cast<int64_t>(p) * stride;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+    const float2 x = load_any_sample(samples, sample_type, base + i);
+    mx = fmaxf(mx, x.x * x.x + x.y * x.y);
+  }
+  const float2* txp = reinterpret_cast<const float2*>(tx) +
+                      (tx_per_pulse ? static_cast<int64_t>(p) * code_len : 0);
+  for (int n = threadIdx.x; n < code_len; n += 256) {
+    const float2 c = txp[n];
+    mc = fmaxf(mc, c.x * c.x + c.y * c.y);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mx = fmaxf(mx, __shfl_xor(mx, off));
+    mc = fmaxf(mc, __shfl_xor(mc, off));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = mx;
+    red[1][threadIdx.x >> 6] = mc;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    mx = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+    mc = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+    int e = 0;
+    const float m = sqrtf(mx) * sqrtf(mc);
+    if (m > 0.f && isfinite(m)) {
+      int ex;
+      frexpf(m, &ex);  // m < 2^ex
+      e = 14 - ex;
+    }
+    exps[p] = max(-60, min(60, e));
+  }
+}
+
+}  // namespace ispl

@@ -94,7 +94,9 @@ struct ZoomArgs {
   const int32_t* gate_count;
 };
 
-hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream);
+// With exponents = false the FP16 column exponents must already be in
+// a.col_exp (launch_select_and_exponents writes them).
+hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream, bool exponents = true);
 
 // Window-proposal network (learned zoom).
 constexpr int NET_LEN = 1024;      // coarse bins per gate
@@ -121,9 +123,12 @@ hipError_t launch_net_loss_grad(const NetWork& w, const float* x, const float* t
 size_t net_bf16_bytes();  // matrix-core weight table of the BF16 forward
 hipError_t launch_net_prep_bf16(const float* params, void* table, hipStream_t s);
 // logits of features x (or, with from_spectra, of coarse spectra x whose
-// features the kernel forms itself)
+// features the kernel forms itself; with chunks > 1 those spectra are first
+// summed from [chunks][batch][1024] partials and written to x_out)
 hipError_t launch_net_forward_bf16(const void* table, const float* x, int batch, float* logits,
-                                   hipStream_t s, bool from_spectra = false);
+                                   hipStream_t s, bool from_spectra = false,
+                                   const float* partial = nullptr, int32_t chunks = 1,
+                                   float* x_out = nullptr);
 hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int n, float lr,
                        int step, hipStream_t s);
 
@@ -137,10 +142,29 @@ hipError_t launch_select_windows(const float* logits, int32_t n_gates, int32_t f
                                  float* confidence, int32_t* flag, int32_t* zoom_list,
                                  int32_t* fallback_list, int32_t* counts, int32_t* done,
                                  hipStream_t s);
-hipError_t launch_split_peaks(const float* window_spectra, const float* full_spectra,
-                              const int32_t* flag, const int32_t* bin_start, int32_t n_gates,
-                              int32_t window_bins, int32_t fine_len, int32_t* peak_bin,
-                              float* peak_power, hipStream_t s);
+// Peak per gate over its window (zoomed) or its full row (fallback); with
+// zoom_chunks or fine_chunks > 1 the rows are first summed from the chunk
+// partials ([C][G][len], ascending c) and written to window_spectra /
+// full_spectra.
+hipError_t launch_split_peaks(float* window_spectra, const float* window_partial,
+                              int32_t zoom_chunks, float* full_spectra, const float* full_partial,
+                              int32_t fine_chunks, const int32_t* flag, const int32_t* bin_start,
+                              int32_t n_gates, int32_t window_bins, int32_t fine_len,
+                              int32_t* peak_bin, float* peak_power, hipStream_t s);
+// Per-pulse FP16 exponents of the zoom DFT (pulses 0 .. n_pulses - 1).
+struct PulseExpArgs {
+  const void* samples;
+  const float* tx;
+  int32_t* exps;
+  int64_t stride, lo, hi;  // rows and the span [lo, hi) some gate reads
+  int32_t sample_type, code_len, tx_per_pulse, n_pulses;
+};
+// select_windows and, in the same launch, the pulse exponents (n_pulses = 0: none).
+hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int32_t fine_len,
+                                       int32_t window_bins, float threshold, int32_t* bin_start,
+                                       float* confidence, int32_t* flag, int32_t* zoom_list,
+                                       int32_t* fallback_list, int32_t* counts, int32_t* done,
+                                       const PulseExpArgs& pe, hipStream_t s);
 hipError_t launch_window_peak(const float* spectra, int32_t n_gates, int32_t window_bins,
                               int32_t fine_len, const int32_t* bin_start, const int32_t* list,
                               const int32_t* count, int32_t* peak_bin, float* peak_power,

@@ -19,6 +19,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "ispl_device.h"
 #include "ispl_internal.h"
 
 namespace ispl {
@@ -102,20 +103,21 @@ __device__ void compact_gates(const int32_t* flag, int32_t n_gates, int32_t* zoo
 }
 
 // One workgroup per gate decides its window; the workgroup that finishes
-// last (a device-scope counter, reset by that workgroup for the next call)
-// compacts the lists, so decision and lists take one launch.
-__global__ void __launch_bounds__(NT)
-select_windows(const float* __restrict__ logits, int32_t n_gates, int32_t fine_len,
-               int32_t window_bins, float threshold, int32_t* __restrict__ bin_start,
-               float* __restrict__ confidence, int32_t* __restrict__ flag,
-               int32_t* __restrict__ zoom_list, int32_t* __restrict__ fallback_list,
-               int32_t* __restrict__ counts, int32_t* __restrict__ done) {
+// last (a device-scope counter over the n_gates deciding workgroups, reset by
+// that workgroup for the next call) compacts the lists, so decision and lists
+// take one launch.
+__device__ __forceinline__ void select_window_block(
+    int g, const float* __restrict__ logits, int32_t n_gates, int32_t fine_len,
+    int32_t window_bins, float threshold, int32_t* __restrict__ bin_start,
+    float* __restrict__ confidence, int32_t* __restrict__ flag, int32_t* __restrict__ zoom_list,
+    int32_t* __restrict__ fallback_list, int32_t* __restrict__ counts,
+    int32_t* __restrict__ done) {
   __shared__ int is_last;
   __shared__ int wtot[NT / 64];
   __shared__ float sv[NT / 64];
   __shared__ int sk[NT / 64];
   __shared__ float red[NT / 64];
-  const int g = blockIdx.x, j = threadIdx.x;
+  const int j = threadIdx.x;
   const float* row = logits + static_cast<int64_t>(g) * T;
   const float4 l4 = reinterpret_cast<const float4*>(row)[j];
   const float l[4] = {l4.x, l4.y, l4.z, l4.w};
@@ -175,6 +177,36 @@ select_windows(const float* __restrict__ logits, int32_t n_gates, int32_t fine_l
   if (j == 0) *done = 0;
 }
 
+__global__ void __launch_bounds__(NT)
+select_windows(const float* __restrict__ logits, int32_t n_gates, int32_t fine_len,
+               int32_t window_bins, float threshold, int32_t* __restrict__ bin_start,
+               float* __restrict__ confidence, int32_t* __restrict__ flag,
+               int32_t* __restrict__ zoom_list, int32_t* __restrict__ fallback_list,
+               int32_t* __restrict__ counts, int32_t* __restrict__ done) {
+  select_window_block(static_cast<int>(blockIdx.x), logits, n_gates, fine_len, window_bins,
+                      threshold, bin_start, confidence, flag, zoom_list, fallback_list, counts,
+                      done);
+}
+
+// The window decision (workgroups g < n_gates) and, in the same launch, the
+// zoom DFT's per-pulse FP16 exponents (workgroup n_gates + p for pulse p).
+__global__ void __launch_bounds__(NT)
+select_and_exponents(const float* __restrict__ logits, int32_t n_gates, int32_t fine_len,
+                     int32_t window_bins, float threshold, int32_t* __restrict__ bin_start,
+                     float* __restrict__ confidence, int32_t* __restrict__ flag,
+                     int32_t* __restrict__ zoom_list, int32_t* __restrict__ fallback_list,
+                     int32_t* __restrict__ counts, int32_t* __restrict__ done, PulseExpArgs pe) {
+  static_assert(NT == 256, "the exponent role runs 256 threads");
+  const int b = static_cast<int>(blockIdx.x);
+  if (b < n_gates) {
+    select_window_block(b, logits, n_gates, fine_len, window_bins, threshold, bin_start,
+                        confidence, flag, zoom_list, fallback_list, counts, done);
+  } else {
+    pulse_exponent_block(pe.samples, pe.sample_type, pe.tx, pe.stride, pe.lo, pe.hi, pe.code_len,
+                         pe.tx_per_pulse, b - n_gates, pe.exps);
+  }
+}
+
 // Peak of each listed gate's window: (value, -local index) maximum of row g
 // of the [n_gates][K] window spectra, reported as the bin (start + j) mod N.
 __global__ void __launch_bounds__(NT)
@@ -212,23 +244,37 @@ window_peak(const float* __restrict__ spectra, int32_t n_gates, int32_t window_b
 
 // Peak of every gate of the learned zoom: over its window when it was zoomed,
 // over the whole full-resolution row otherwise (ties to the lowest bin, NaN
-// never wins).
+// never wins).  When the zoom or the fallback launch split its pulses into
+// chunks, the gate's row is first summed from the chunk partials in ascending
+// chunk order (the order of the separate chunk reduction) and written out.
 __global__ void __launch_bounds__(NT)
-split_peaks(const float* __restrict__ window_spectra, const float* __restrict__ full_spectra,
+split_peaks(float* __restrict__ window_spectra, const float* __restrict__ window_partial,
+            int32_t zoom_chunks, float* __restrict__ full_spectra,
+            const float* __restrict__ full_partial, int32_t fine_chunks,
             const int32_t* __restrict__ flag, const int32_t* __restrict__ bin_start,
-            int32_t window_bins, int32_t fine_len, int32_t* __restrict__ peak_bin,
+            int32_t n_gates, int32_t window_bins, int32_t fine_len, int32_t* __restrict__ peak_bin,
             float* __restrict__ peak_power) {
   __shared__ float sv[NT / 64];
   __shared__ int sk[NT / 64];
   const int g = blockIdx.x;
   const bool zoomed = flag[g] != 0;
   const int len = zoomed ? window_bins : fine_len;
-  const float* row = zoomed ? window_spectra + static_cast<int64_t>(g) * window_bins
-                            : full_spectra + static_cast<int64_t>(g) * fine_len;
+  float* row = zoomed ? window_spectra + static_cast<int64_t>(g) * window_bins
+                      : full_spectra + static_cast<int64_t>(g) * fine_len;
+  const int chunks = zoomed ? zoom_chunks : fine_chunks;
+  const float* part = (zoomed ? window_partial : full_partial) + static_cast<int64_t>(g) * len;
+  const int64_t cstride = static_cast<int64_t>(n_gates) * len;
   float bv = -INFINITY;
   int bk = INT_MAX;
   for (int i = threadIdx.x; i < len; i += NT) {
-    const float v = row[i];
+    float v;
+    if (chunks > 1) {
+      v = 0.f;
+      for (int c = 0; c < chunks; ++c) v += part[c * cstride + i];
+      row[i] = v;
+    } else {
+      v = row[i];
+    }
     if (better(v, i, bv, bk)) {
       bv = v;
       bk = i;
@@ -236,7 +282,7 @@ split_peaks(const float* __restrict__ window_spectra, const float* __restrict__ 
   }
   block_argmax(bv, bk, sv, sk);
   if (threadIdx.x == 0) {
-    if (bk == INT_MAX) {  // only NaN
+    if (bk == INT_MAX) {  // only NaN; thread 0 itself formed bin 0
       bk = 0;
       bv = row[0];
     }
@@ -264,13 +310,27 @@ hipError_t launch_select_windows(const float* logits, int32_t n_gates, int32_t f
   return hipGetLastError();
 }
 
-hipError_t launch_split_peaks(const float* window_spectra, const float* full_spectra,
-                              const int32_t* flag, const int32_t* bin_start, int32_t n_gates,
-                              int32_t window_bins, int32_t fine_len, int32_t* peak_bin,
-                              float* peak_power, hipStream_t s) {
+hipError_t launch_split_peaks(float* window_spectra, const float* window_partial,
+                              int32_t zoom_chunks, float* full_spectra, const float* full_partial,
+                              int32_t fine_chunks, const int32_t* flag, const int32_t* bin_start,
+                              int32_t n_gates, int32_t window_bins, int32_t fine_len,
+                              int32_t* peak_bin, float* peak_power, hipStream_t s) {
   hipLaunchKernelGGL(split_peaks, dim3(static_cast<unsigned>(n_gates)), dim3(NT), 0, s,
-                     window_spectra, full_spectra, flag, bin_start, window_bins, fine_len, peak_bin,
+                     window_spectra, window_partial, zoom_chunks, full_spectra, full_partial,
+                     fine_chunks, flag, bin_start, n_gates, window_bins, fine_len, peak_bin,
                      peak_power);
+  return hipGetLastError();
+}
+
+hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int32_t fine_len,
+                                       int32_t window_bins, float threshold, int32_t* bin_start,
+                                       float* confidence, int32_t* flag, int32_t* zoom_list,
+                                       int32_t* fallback_list, int32_t* counts, int32_t* done,
+                                       const PulseExpArgs& pe, hipStream_t s) {
+  const unsigned blocks = static_cast<unsigned>(n_gates) + static_cast<unsigned>(pe.n_pulses);
+  hipLaunchKernelGGL(select_and_exponents, dim3(blocks), dim3(NT), 0, s, logits, n_gates,
+                     fine_len, window_bins, threshold, bin_start, confidence, flag, zoom_list,
+                     fallback_list, counts, done, pe);
   return hipGetLastError();
 }
 

@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ispl_device.h"
 #include "ispl_internal.h"
 
 namespace ispl {
@@ -371,50 +372,13 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
   }
 }
 
-// Per-pulse FP16 exponent: 2^e with max|x| max|c| 2^e < 2^14 over the samples
-// every gate of the pulse reads, so no split value overflows and the low
-// halves stay normal down to about 2^-17 of that maximum.
+// Per-pulse FP16 exponents, one workgroup per pulse.
 __global__ void __launch_bounds__(256)
 pulse_exponents(const void* __restrict__ samples, int32_t sample_type, const float* __restrict__ tx,
                 int64_t stride, int64_t lo, int64_t hi, int32_t code_len, int32_t tx_per_pulse,
                 int32_t* __restrict__ exps) {
-  __shared__ float red[2][4];
-  const int p = blockIdx.x;
-  float mx = 0.f, mc = 0.f;
-  const int64_t base = static_cast<int64_t>(p) * stride;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
-    const float2 x = sample_type == 1 ? load_sample<1>(samples, base + i)
-                                      : load_sample<0>(samples, base + i);
-    mx = fmaxf(mx, x.x * x.x + x.y * x.y);
-  }
-  const float2* txp = reinterpret_cast<const float2*>(tx) +
-                      (tx_per_pulse ? static_cast<int64_t>(p) * code_len : 0);
-  for (int n = threadIdx.x; n < code_len; n += 256) {
-    const float2 c = txp[n];
-    mc = fmaxf(mc, c.x * c.x + c.y * c.y);
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    mx = fmaxf(mx, __shfl_xor(mx, off));
-    mc = fmaxf(mc, __shfl_xor(mc, off));
-  }
-  if ((threadIdx.x & 63) == 0) {
-    red[0][threadIdx.x >> 6] = mx;
-    red[1][threadIdx.x >> 6] = mc;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    mx = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
-    mc = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
-    int e = 0;
-    const float m = sqrtf(mx) * sqrtf(mc);
-    if (m > 0.f && isfinite(m)) {
-      int ex;
-      frexpf(m, &ex);  // m < 2^ex
-      e = 14 - ex;
-    }
-    exps[p] = max(-60, min(60, e));
-  }
+  pulse_exponent_block(samples, sample_type, tx, stride, lo, hi, code_len, tx_per_pulse,
+                       static_cast<int>(blockIdx.x), exps);
 }
 
 template <int PREC, int ST, int RT>
@@ -443,13 +407,15 @@ hipError_t launch_zoom_t(const ZoomArgs& a, hipStream_t stream) {
 
 }  // namespace
 
-hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream) {
+hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream, bool exponents) {
   if (a.precision == 1) {
-    hipLaunchKernelGGL(pulse_exponents, dim3(static_cast<unsigned>(a.n_pulses)), dim3(256), 0,
-                       stream, a.samples, a.sample_type, a.tx, a.stride, a.row_lo, a.row_hi,
-                       a.code_len, a.tx_per_pulse, a.col_exp);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (exponents) {
+      hipLaunchKernelGGL(pulse_exponents, dim3(static_cast<unsigned>(a.n_pulses)), dim3(256), 0,
+                         stream, a.samples, a.sample_type, a.tx, a.stride, a.row_lo, a.row_hi,
+                         a.code_len, a.tx_per_pulse, a.col_exp);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
     return launch_zoom_t<1>(a, stream);
   }
   return launch_zoom_t<0>(a, stream);

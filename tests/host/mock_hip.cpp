@@ -331,17 +331,18 @@ hipError_t launch_fill_zero_rows(float* dst, int32_t g, int32_t n, const int32_t
   run_on(st, [=] { check_range(dst, size_t(g) * n * 4, "fill_zero_rows"); });
   return hipSuccess;
 }
-hipError_t launch_zoom(const ZoomArgs&, hipStream_t) { return hipSuccess; }
+hipError_t launch_zoom(const ZoomArgs&, hipStream_t, bool) { return hipSuccess; }
 hipError_t launch_net_features(const float*, int, float*, hipStream_t) { return hipSuccess; }
 hipError_t launch_net_forward_f32(const NetWork&, const float*, int, float*, hipStream_t) { return hipSuccess; }
 hipError_t launch_net_loss_grad(const NetWork&, const float*, const float*, int, float*, float*, hipStream_t) { return hipSuccess; }
 size_t net_bf16_bytes() { return 65536; }
 hipError_t launch_net_prep_bf16(const float*, void*, hipStream_t) { return hipSuccess; }
-hipError_t launch_net_forward_bf16(const void*, const float*, int, float*, hipStream_t, bool) { return hipSuccess; }
+hipError_t launch_net_forward_bf16(const void*, const float*, int, float*, hipStream_t, bool, const float*, int32_t, float*) { return hipSuccess; }
 hipError_t launch_adam(float*, const float*, float*, float*, int, float, int, hipStream_t) { return hipSuccess; }
 hipError_t launch_peak(const float*, int32_t, int32_t, int32_t, int32_t, int32_t*, float*, const int32_t*, const int32_t*, hipStream_t) { return hipSuccess; }
 hipError_t launch_select_windows(const float*, int32_t, int32_t, int32_t, float, int32_t*, float*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, hipStream_t) { return hipSuccess; }
-hipError_t launch_split_peaks(const float*, const float*, const int32_t*, const int32_t*, int32_t, int32_t, int32_t, int32_t*, float*, hipStream_t) { return hipSuccess; }
+hipError_t launch_split_peaks(float*, const float*, int32_t, float*, const float*, int32_t, const int32_t*, const int32_t*, int32_t, int32_t, int32_t, int32_t*, float*, hipStream_t) { return hipSuccess; }
+hipError_t launch_select_and_exponents(const float*, int32_t, int32_t, int32_t, float, int32_t*, float*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, const PulseExpArgs&, hipStream_t) { return hipSuccess; }
 hipError_t launch_window_peak(const float*, int32_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*, int32_t*, float*, hipStream_t) { return hipSuccess; }
 
 }  // namespace ispl

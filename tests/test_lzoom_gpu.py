@@ -214,7 +214,15 @@ def test_learned_zoom_composes_building_blocks_and_matches_oracle(ispl):
     lz = ispl.LearnedZoom(net, window_bins=K, fft_len=N, threshold=thr, **geo)
     bins, power = lz.peaks(xs, xt)
     torch.cuda.synchronize()
-    # by hand, through the building blocks
+    # the object's coarse spectra: the plain path at N = 1024, its pulses split
+    # into other chunks (rounding only)
+    coarse_lz = lz.view()["coarse_spectra"].clone()
+    plain_coarse = coarse.integrate_spectra(xs, xt)
+    torch.cuda.synchronize()
+    scale = torch.maximum(plain_coarse, plain_coarse.mean(dim=1, keepdim=True))
+    assert float(((coarse_lz - plain_coarse).abs() / scale).max()) <= 1e-6
+    # by hand, through the building blocks, from the same coarse spectra
+    logits = net.forward(net.features(coarse_lz), precision="bf16")
     sel = net.select(logits, N, K, thr)
     zoom = ispl.Zoom(fine, K, "fp16x3")
     gz = (sel["zoom_list"], sel["counts"][0:1])
