@@ -318,7 +318,10 @@ __device__ __forceinline__ float* out_row(const FusedArgs& a, int g, int c) {
 
 // Code lengths L <= 1024: one wave per bin class k1 (sub-transform length 1024).
 // RW waves share a gate and a pulse: the decoded row is staged once in LDS.
-template <int RW, int ST>
+// PF (one-wave workgroups only): fetch the next pulse during this pulse's
+// transform, for launches too small to hide memory latency with other waves
+// (the extra registers cost a wave per SIMD on large launches).
+template <int RW, int ST, bool PF = false>
 __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   constexpr int NT = 64 * RW;
   constexpr int E = SUB / NT;          // decoded samples staged per thread
@@ -380,16 +383,26 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   if constexpr (RW == 1) {
     // One wave owns the gate: thread tid loads samples tid + 64 i, which are
     // exactly its pass-1 inputs, so the row needs no LDS stage and no barrier.
-    // The next pulse's samples and codes are fetched before this pulse's
-    // transform, so a wave that is alone on its SIMD (few gates, short pulse
-    // chunks) does not wait for memory once per pulse.
-    if (p0 < p1) load(p0);
-    for (int p = p0; p < p1; ++p) {
-      float2 v[16];
+    if constexpr (PF) {
+      // the next pulse's samples and codes are in flight during this pulse's
+      // transform, so a wave alone on its SIMD does not wait once per pulse
+      if (p0 < p1) load(p0);
+      for (int p = p0; p < p1; ++p) {
+        float2 v[16];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
-      if (p + 1 < p1) load(p + 1);
-      wave_fft_accumulate(v, xw, wt, dk, acc, lane);
+        for (int j = 0; j < 16; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
+        if (p + 1 < p1) load(p + 1);
+        wave_fft_accumulate(v, xw, wt, dk, acc, lane);
+      }
+    } else {
+      // the other waves on the SIMD hide the load latency
+      for (int p = p0; p < p1; ++p) {
+        load(p);
+        float2 v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
+        wave_fft_accumulate(v, xw, wt, dk, acc, lane);
+      }
     }
   } else {
   if (p0 < p1) load(p0);
@@ -630,7 +643,16 @@ template <int RW, int ST>
 hipError_t launch_fused_t(const FusedArgs& a, hipStream_t stream) {
   const int zgroups = (1 << a.log2_r) / RW;
   const int64_t blocks = static_cast<int64_t>(a.n_gates) * zgroups * a.chunks;
-  hipLaunchKernelGGL((fused_spectra<RW, ST>), dim3(static_cast<unsigned>(blocks)),
+  // one-wave workgroups prefetch when the launch has at most two waves per SIMD
+  constexpr int64_t kPrefetchMaxWaves = 2 * 4 * 256;
+  if constexpr (RW == 1) {
+    if (blocks <= kPrefetchMaxWaves) {
+      hipLaunchKernelGGL((fused_spectra<1, ST, true>), dim3(static_cast<unsigned>(blocks)),
+                         dim3(64), 0, stream, a);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((fused_spectra<RW, ST, false>), dim3(static_cast<unsigned>(blocks)),
                      dim3(64 * RW), 0, stream, a);
   return hipGetLastError();
 }
