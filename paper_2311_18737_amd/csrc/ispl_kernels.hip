@@ -446,7 +446,31 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
 // DFT over j (pre-twiddled by W_N^{1024 k1 j}); an all-to-all exchange through
 // LDS then hands wave ka the values U_ka[lg], whose 1024-point transform, with
 // the bin-class factor W_N^{lg (k1 + R ka)}, is bins k1 + R (ka + 16 kb).
+// TWO: codes of at most 2048 samples, so only j = 0, 1 carry samples.  The
+// first pass is then X[k] = y0 + t W_16^k with t = y1 W_N^{1024 k1} (half of
+// the outputs as y0 + t W_16^k, the other half as y0 - t W_16^k), and the two
+// samples and codes of the next pulse are fetched during this pulse's work.
 template <int ST>
+__device__ __forceinline__ void two_point_pass(float2 (&v)[16], float2 y0, float2 t,
+                                               const Dft16Consts& k) {
+  // u_m = t W_16^m for m < 8, W_16^m = exp(-2 pi i m / 16)
+  float2 u[8];
+  u[0] = t;
+  u[1] = cmul(t, make_float2(k.c8, -k.s8));
+  u[2] = make_float2(k.r2 * (t.x + t.y), k.r2 * (t.y - t.x));
+  u[3] = cmul(t, make_float2(k.s8, -k.c8));
+  u[4] = make_float2(t.y, -t.x);
+  u[5] = cmul(t, make_float2(-k.s8, -k.c8));
+  u[6] = make_float2(k.r2 * (t.y - t.x), -k.r2 * (t.x + t.y));
+  u[7] = cmul(t, make_float2(-k.c8, -k.s8));
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    v[m] = make_float2(y0.x + u[m].x, y0.y + u[m].y);
+    v[m + 8] = make_float2(y0.x - u[m].x, y0.y - u[m].y);
+  }
+}
+
+template <int ST, bool TWO>
 __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
   using IO = SampleIO<ST>;
   __shared__ float2 xs[16 * XWAVE];
@@ -483,17 +507,45 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
   const float2* __restrict__ txb = reinterpret_cast<const float2*>(a.tx);
   float2* xw = xs + wave * XWAVE;
 
-  for (int p = p0; p < p1; ++p) {
+  // TWO: samples and codes of slices j = 0, 1 of the next pulse
+  using raw_t = typename IO::raw_t;
+  raw_t nr[2] = {IO::zero(), IO::zero()};
+  float2 nc[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+  auto fetch2 = [&](int p) {
     const int64_t rowp = static_cast<int64_t>(p) * a.stride + gate_off;
     const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0);
-    float2 v[16];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < 2; ++j) {
       const int n = tid + 1024 * j;
-      v[j] = n < L ? conj_mul(txp[n], IO::cvt(IO::load(a.samples, rowp + n)))
-                   : make_float2(0.f, 0.f);
+      if (n < L) {
+        nr[j] = IO::load(a.samples, rowp + n);
+        nc[j] = txp[n];
+      } else {
+        nr[j] = IO::zero();
+        nc[j] = make_float2(0.f, 0.f);
+      }
     }
-    dft16_pre1(v, xpre, dk);
+  };
+  if (TWO && p0 < p1) fetch2(p0);
+
+  for (int p = p0; p < p1; ++p) {
+    float2 v[16];
+    if constexpr (TWO) {
+      const float2 y0 = conj_mul(nc[0], IO::cvt(nr[0]));
+      const float2 y1 = conj_mul(nc[1], IO::cvt(nr[1]));
+      if (p + 1 < p1) fetch2(p + 1);
+      two_point_pass<ST>(v, y0, cmul(y1, xpre[1]), dk);
+    } else {
+      const int64_t rowp = static_cast<int64_t>(p) * a.stride + gate_off;
+      const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0);
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int n = tid + 1024 * j;
+        v[j] = n < L ? conj_mul(txp[n], IO::cvt(IO::load(a.samples, rowp + n)))
+                     : make_float2(0.f, 0.f);
+      }
+      dft16_pre1(v, xpre, dk);
+    }
     __syncthreads();  // every wave has finished its exchanges of the previous pulse
 #pragma unroll
     for (int k = 0; k < 16; ++k) xs[k * XWAVE + tid] = v[k];  // region k: U_k[lg]
@@ -660,8 +712,12 @@ hipError_t launch_fused_t(const FusedArgs& a, hipStream_t stream) {
 template <int ST>
 hipError_t launch_fused_long_t(const FusedArgs& a, hipStream_t stream) {
   const int64_t blocks = static_cast<int64_t>(a.n_gates) * (1 << a.log2_r) * a.chunks;
-  hipLaunchKernelGGL((fused_spectra_long<ST>), dim3(static_cast<unsigned>(blocks)), dim3(1024), 0,
-                     stream, a);
+  if (a.code_len <= 2 * SUB)
+    hipLaunchKernelGGL((fused_spectra_long<ST, true>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(1024), 0, stream, a);
+  else
+    hipLaunchKernelGGL((fused_spectra_long<ST, false>), dim3(static_cast<unsigned>(blocks)),
+                       dim3(1024), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -75,6 +75,9 @@ SHAPES = [
     (16384, 1025, 2, 3, 7, 0, "c64", False, "gauss"),
     (32768, 2000, 3, 4, 25, 5, "ci16", True, "bpsk"),
     (65536, 4000, 2, 2, 100, 3, "ci16", True, "phase"),
+    # the two-slice variant (L <= 2048) at its edge, and one sample past it
+    (16384, 2048, 2, 5, 9, 2, "c64", True, "gauss"),
+    (16384, 2049, 2, 3, 9, 0, "ci16", False, "bpsk"),
 ]
 
 
