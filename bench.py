@@ -328,12 +328,21 @@ def batch_study(steps: int, seed: int, dev):
     t_seq = timed(sequential)
     b = ispl.Batch(geo)
     outs = [torch.empty_like(o) for o in seq_out]
+    graph_ms = {}
     try:
         plan, tuned_ms = b.tune(data, outs, trials=3)
         log(f"batch: tuned plan {plan} ({tuned_ms:.3f} ms)")
     except ispl.IsplError as err:  # autotuner switched off in this build
-        plan, tuned_ms = b.plan(), None
-        log(f"batch: automatic plan {plan} ({err})")
+        # automatic tile shapes; of the two graph shapes (a parallel branch per
+        # experiment, or one serial branch) keep the faster
+        tuned_ms = None
+        for serial in (False, True):
+            b.set_plan(serial=serial)
+            graph_ms["serial" if serial else "parallel"] = timed(
+                lambda: b.integrate(data, outs, use_graph=True, stream=stream))
+        b.set_plan(serial=graph_ms["serial"] < graph_ms["parallel"])
+        plan = b.plan()
+        log(f"batch: automatic plan {plan}, graph shapes {graph_ms} ({err})")
     t_batch = timed(lambda: b.integrate(data, outs, use_graph=True, stream=stream))
     torch.cuda.synchronize()
     worst = 0.0
@@ -347,7 +356,7 @@ def batch_study(steps: int, seed: int, dev):
            "batch_ms": t_batch, "sequential_ms": t_seq, "speedup_vs_sequential": t_seq / t_batch,
            "spectra_per_s": units / (t_batch / 1e3),
            "nominal_TFLOPs": flops / (t_batch / 1e3) / 1e12,
-           "plan": plan, "tuned_ms": tuned_ms,
+           "plan": plan, "tuned_ms": tuned_ms, "graph_shape_ms": graph_ms or None,
            "max_rel_diff_vs_sequential": worst}
     log(f"batch: {out}")
     b.close()
