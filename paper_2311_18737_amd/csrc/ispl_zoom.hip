@@ -19,14 +19,15 @@
 // before the pulse sum.  Decode,
 // shift and pulse integration run in FP32.
 //
-// Tiling: a workgroup of 8 waves owns one gate, 128 or 256 bins (one or two
-// 32-row MFMA tiles per wave) and a chunk of the pulses, which it sweeps in
-// blocks of 32 or 64 columns (one or two 32x32 tiles).  The decoded, shifted and
-// split samples of a block are built per 64-sample chunk in LDS in the MFMA
-// B-operand layout, double-buffered so that building overlaps the matrix
-// work; the A operand (DFT matrix, split) streams from a table laid out in
-// the A-operand order, 16 bytes per lane per k-step, one k-step ahead.  Pulse
-// chunks of one gate write partial windows that a fixed-order pass sums.
+// Tiling: a workgroup owns one gate, 128 or 256 bins and a chunk of the
+// pulses, which it sweeps in blocks of 32 or 64 columns (one or two 32x32
+// tiles).  Eight matrix waves hold one or two 32-row MFMA tiles each; four
+// building waves decode, shift and split the samples of the next 64-sample
+// chunk into LDS, in the MFMA B-operand layout, while the matrix waves
+// multiply the current one (double buffer).  The A operand (DFT matrix,
+// split) streams from a table laid out in the A-operand order, 16 bytes per
+// lane per k-step, two k-steps ahead.  Pulse chunks of one gate write
+// partial windows that a fixed-order pass sums.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -41,8 +42,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int ZW = 8;              // waves per workgroup
-constexpr int ZT = 64 * ZW;        // threads
+constexpr int ZW = 8;              // matrix waves per workgroup
+constexpr int ZP = 4;              // building waves per workgroup
+constexpr int ZTA = 64 * (ZW + ZP);  // threads
 constexpr int ZCHUNK = 64;         // samples per B chunk (8 MFMA k-steps of 16 rows)
 constexpr int ZKS = 2 * ZCHUNK / 16;
 
@@ -97,19 +99,17 @@ __device__ __forceinline__ float2 load_sample(const void* base, int64_t i) {
   }
 }
 
-// One 64-sample chunk of the B operand.  A thread builds items (column pc,
-// group qg of 4 consecutive samples) with qg = tid % 16 fixed and pc = tid / 16
-// + (ZT / 16) i, so the 16 lanes of one column read one contiguous run of the
-// pulse row (and of its code).  load_chunk fetches the samples, codes and shift
-// twiddles and can be in flight while the matrix cores work on the previous
-// chunk; every load is unconditional (indices clamped into the row), so the
-// compiler's memory counters wait for exactly the loads a use needs.
-// store_chunk zeroes samples past L and pulses past the chunk, decodes, shifts,
-// scales and splits them into high and low halves and stores them in the MFMA
-// B layout (k-step qg / 2, lane half qg % 2).
-template <int CT>
+// One 64-sample chunk of the B operand.  A building thread owns items (column
+// pc, group qg of 4 consecutive samples) with qg = thread % 16 fixed and pc =
+// thread / 16 + CS i, so the 16 lanes of one column read one contiguous run of
+// the pulse row (and of its code).  load_chunk fetches the samples, codes and
+// shift twiddles (indices clamped into the row, so every load is valid);
+// store_chunk zeroes samples past L and pulses past the chunk, decodes,
+// shifts, scales and splits them into high and low halves and stores them in
+// the MFMA B layout (k-step qg / 2, lane half qg % 2).
+template <int NI>
 struct ChunkRegs {
-  float2 x[CT][4], c[CT][4], w[CT][4];
+  float2 x[NI][4], c[NI][4], w[NI][4];
 };
 
 // Column pc's B fragment of k-step ks sits at slot lane ^ swz(ks, lane) of the
@@ -123,14 +123,14 @@ struct ItemCtx {
   bool live;           // pulse inside the chunk
 };
 
-template <int ST, int CT>
-__device__ __forceinline__ void load_chunk(const ZoomArgs& a, ChunkRegs<CT>& r, int ch, int qg,
-                                           const ItemCtx (&it)[CT], uint32_t k0) {
+template <int ST, int NI>
+__device__ __forceinline__ void load_chunk(const ZoomArgs& a, ChunkRegs<NI>& r, int ch, int qg,
+                                           const ItemCtx (&it)[NI], uint32_t k0) {
   const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
   const uint32_t nmask = static_cast<uint32_t>(a.n_fft - 1);
   const int L = a.code_len;
 #pragma unroll
-  for (int i = 0; i < CT; ++i)
+  for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
       const int n = ch * ZCHUNK + 4 * qg + s2;
@@ -142,14 +142,15 @@ __device__ __forceinline__ void load_chunk(const ZoomArgs& a, ChunkRegs<CT>& r, 
     }
 }
 
-template <int PREC, int CT>
-__device__ __forceinline__ void store_chunk(const ChunkRegs<CT>& r, Frag (*bh)[ZKS][64],
+// Item i of the thread is column pc0 + CS i.
+template <int PREC, int NI, int CS>
+__device__ __forceinline__ void store_chunk(const ChunkRegs<NI>& r, Frag (*bh)[ZKS][64],
                                             Frag (*bl)[ZKS][64], int pc0, int qg,
-                                            const float (&scale)[CT], const ItemCtx (&it)[CT],
+                                            const float (&scale)[NI], const ItemCtx (&it)[NI],
                                             int ch, int L) {
 #pragma unroll
-  for (int i = 0; i < CT; ++i) {
-    const int pc = pc0 + (ZT / 16) * i;
+  for (int i = 0; i < NI; ++i) {
+    const int pc = pc0 + CS * i;
     Frag fh, fl;
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
@@ -184,13 +185,15 @@ __device__ __forceinline__ int zoom_xcd_id(int b, int nblk) {
 
 // RT: 32-row MFMA tiles per wave (16 bins each); CT: 32-pulse column tiles per
 // pulse block.  A workgroup owns one gate, 128 RT bins and one chunk of the
-// pulses.  The B chunks are double-buffered in LDS: the next chunk's samples
-// are fetched before the current chunk's matrix work and stored after it (one
-// barrier per chunk), and the A fragments of the next k-step are loaded while
-// the current ones are multiplied.
+// pulses.  Its waves have two roles: ZW matrix waves multiply, ZP building
+// waves fetch, decode and split the samples of the next 64-sample chunk into
+// the other half of a double-buffered LDS B operand at the same time (one
+// barrier per chunk; both roles pass the same number of barriers).  The
+// matrix waves stream their A fragments through a two-deep register ring.
 template <int PREC, int ST, int RT, int CT>
-__global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
+__global__ void __launch_bounds__(ZTA) zoom_spectra(ZoomArgs a) {
   constexpr int NCOL = 32 * CT;
+  constexpr int NI = NCOL / 16;        // items per building thread
   __shared__ Frag bh[2][CT][ZKS][64];  // B operand, high parts: [buffer][tile][k-step][lane]
   __shared__ Frag bl[2][CT][ZKS][64];  // low parts
 
@@ -221,10 +224,46 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
   const int p1 = static_cast<int>((static_cast<int64_t>(chunk + 1) * a.n_pulses) / a.chunks);
   const int nchunks = a.code_pad / ZCHUNK;
   const int n_ks = nchunks * ZKS;
-  const uint32_t k0 = static_cast<uint32_t>(((a.bin_start[g] % N) + N) % N);
-  const float2* __restrict__ txb = reinterpret_cast<const float2*>(a.tx);
-  const int64_t gate_off = static_cast<int64_t>(a.first_gate) + static_cast<int64_t>(g) * a.gate_step;
 
+  if (wave >= ZW) {
+    // ---- building waves ----
+    const uint32_t k0 = static_cast<uint32_t>(((a.bin_start[g] % N) + N) % N);
+    const float2* __restrict__ txb = reinterpret_cast<const float2*>(a.tx);
+    const int64_t gate_off =
+        static_cast<int64_t>(a.first_gate) + static_cast<int64_t>(g) * a.gate_step;
+    const int bt_id = tid - 64 * ZW;
+    const int qg = bt_id & 15, pc0 = bt_id >> 4;
+    static_assert(64 * ZP / 16 * NI == NCOL, "items cover the block's columns");
+    for (int pb = p0; pb < p1; pb += NCOL) {
+      ItemCtx it[NI];
+      float scale[NI];
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        const int p = pb + pc0 + 16 * i;
+        const bool live = p < p1;
+        const int pr = live ? p : p0;
+        it[i].rowp = static_cast<int64_t>(pr) * a.stride + gate_off;
+        it[i].txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(pr) * L : 0);
+        it[i].live = live;
+        scale[i] = (PREC == 1 && live) ? ldexpf(1.f, a.col_exp[p]) : 1.f;
+      }
+      ChunkRegs<NI> cr;
+      load_chunk<ST, NI>(a, cr, 0, qg, it, k0);
+      store_chunk<PREC, NI, 16>(cr, bh[0], bl[0], pc0, qg, scale, it, 0, L);
+      __syncthreads();
+      for (int ch = 0; ch < nchunks; ++ch) {
+        if (ch + 1 < nchunks) {  // chunk ch + 1 while the matrix waves work on chunk ch
+          load_chunk<ST, NI>(a, cr, ch + 1, qg, it, k0);
+          store_chunk<PREC, NI, 16>(cr, bh[(ch + 1) & 1], bl[(ch + 1) & 1], pc0, qg, scale, it,
+                                    ch + 1, L);
+        }
+        __syncthreads();
+      }
+    }
+    return;
+  }
+
+  // ---- matrix waves ----
   // A operand of this wave: row tiles (bt ZW + wave) RT + r, k-steps along the code
   const Frag* __restrict__ ah_t[RT];
   const Frag* __restrict__ al_t[RT];
@@ -240,10 +279,6 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
   for (int r = 0; r < RT; ++r)
 #pragma unroll
     for (int i = 0; i < 8; ++i) total[r][i] = 0.f;
-
-  // B-building role: sample group qg of columns pc0 + (ZT / 16) i
-  const int qg = tid & 15, pc0 = tid >> 4;
-  static_assert(ZT / 16 * CT == NCOL, "one item per thread and column tile");
 
   // A fragments are fetched AD k-steps ahead into a ring (slot ks % AD, which
   // AD | ZKS makes static).  The refill after the last k-step of a pulse
@@ -261,19 +296,6 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
     }
 
   for (int pb = p0; pb < p1; pb += NCOL) {
-    ItemCtx it[CT];
-    float scale[CT];
-#pragma unroll
-    for (int i = 0; i < CT; ++i) {
-      const int p = pb + pc0 + (ZT / 16) * i;
-      const bool live = p < p1;
-      const int pr = live ? p : p0;
-      it[i].rowp = static_cast<int64_t>(pr) * a.stride + gate_off;
-      it[i].txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(pr) * L : 0);
-      it[i].live = live;
-      scale[i] = (PREC == 1 && live) ? ldexpf(1.f, a.col_exp[p]) : 1.f;
-    }
-
     f32x16 acc[RT][CT];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
@@ -281,17 +303,9 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
       for (int ct = 0; ct < CT; ++ct)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[r][ct][i] = 0.f;
-
-    ChunkRegs<CT> cr;
-    load_chunk<ST, CT>(a, cr, 0, qg, it, k0);
-    store_chunk<PREC, CT>(cr, bh[0], bl[0], pc0, qg, scale, it, 0, L);
-    __syncthreads();
+    __syncthreads();  // chunk 0 is built
     for (int ch = 0; ch < nchunks; ++ch) {
       const int b = ch & 1;
-      const bool more = ch + 1 < nchunks;
-      // in flight below; the last chunk re-reads itself instead of branching,
-      // so no later wait has to cover a path without these loads
-      load_chunk<ST, CT>(a, cr, more ? ch + 1 : ch, qg, it, k0);
 #pragma unroll
       for (int ks = 0; ks < ZKS; ++ks) {
         const int slot = ks % AD;
@@ -314,12 +328,8 @@ __global__ void __launch_bounds__(ZT) zoom_spectra(ZoomArgs a) {
           al[slot][r] = al_t[r][static_cast<int64_t>(kn) * 64];
         }
       }
-      // unconditional too (after the last chunk it fills the idle buffer), so
-      // the compiler keeps the loads above the matrix work
-      store_chunk<PREC, CT>(cr, bh[b ^ 1], bl[b ^ 1], pc0, qg, scale, it, more ? ch + 1 : ch, L);
-      __syncthreads();
+      __syncthreads();  // chunk ch is consumed, chunk ch + 1 is built
     }
-
     // |Z|^2 per (bin, pulse).  D row (i % 4) + 8 (i / 4) + 4 h (h = lane / 32) is Re
     // (even) or Im (odd) of tile bin row / 2: registers 4 qa + 2 s and 4 qa + 2 s + 1
     // are bin s + 4 qa + 2 h of the tile.
@@ -386,9 +396,9 @@ hipError_t launch_zoom_rt(const ZoomArgs& a, int ct, hipStream_t stream) {
   const unsigned blocks =
       static_cast<unsigned>(a.n_gates) * (a.n_bins / (128 * RT)) * static_cast<unsigned>(a.chunks);
   if (ct == 1)
-    hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 1>), dim3(blocks), dim3(ZT), 0, stream, a);
+    hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 1>), dim3(blocks), dim3(ZTA), 0, stream, a);
   else if (ct == 2)
-    hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 2>), dim3(blocks), dim3(ZT), 0, stream, a);
+    hipLaunchKernelGGL((zoom_spectra<PREC, ST, RT, 2>), dim3(blocks), dim3(ZTA), 0, stream, a);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
