@@ -268,14 +268,19 @@ ispl_status ispl_net_select(ispl_net* net, const float* logits, int32_t n_gates,
 
 /*
  * Learned zoom: peak frequency of every gate without the full-resolution
- * spectrum of every gate.  One call runs, on `stream`:
- *   1. ispl_integrate_spectra at N_c = 1024 (the coarse spectra);
+ * spectrum of every gate.  One call runs, on `stream`, what these calls
+ * compute one after another (in six launches):
+ *   1. ispl_integrate_spectra at N_c = 1024 (the coarse spectra; its pulses
+ *      are split into chunks of at least 4, so the coarse sums may differ
+ *      from a context's own in rounding);
  *   2. the network's features and BF16 logits;
  *   3. ispl_net_select with (cfg->fft_len, window_bins, threshold);
  *   4. ispl_zoom_spectra_gates over the zoomed gates (window_bins bins from
  *      bin_start, zoom_precision) and ispl_integrate_spectra_gates at
  *      cfg->fft_len over the fallback gates;
  *   5. ispl_zoom_find_peaks and ispl_find_plasma_line_gates (full band).
+ * Given the coarse spectra of step 1, steps 2-5 equal those calls bit for
+ * bit.
  * peak_bin[g] / peak_power[g] (device int32 / float [n_gates]; peak_power
  * may be NULL) then hold every gate's line bin at N = cfg->fft_len.
  * ispl_lzoom_create: cfg as for ispl_create with code_len <= 1024 and
