@@ -195,8 +195,9 @@ def test_select_large_gate_count_compaction(ispl):
     net.close()
 
 
-def test_learned_zoom_composes_building_blocks_and_matches_oracle(ispl):
-    cfg = CONFIGS["zoom"].replace(n_pulses=20)
+@pytest.mark.parametrize("n_pulses", [20, 60])  # 60: the zoom also splits its pulses
+def test_learned_zoom_composes_building_blocks_and_matches_oracle(ispl, n_pulses):
+    cfg = CONFIGS["zoom"].replace(n_pulses=n_pulses)
     d = make_dataset(cfg, 5, cache_dir=None)
     N, K, G, S = cfg.fft_len, 256, cfg.n_gates, cfg.fft_len // 1024
     params = cnn.init_params(2).astype(np.float32)
