@@ -62,6 +62,8 @@ SHAPES = [
     (1024, 1, 1, 1, 1, 0, "c64", True, "phase"),
     (1024, 1024, 3, 5, 7, 3, "ci16", False, "bpsk"),
     (1024, 256, 17, 33, 25, 0, "c64", True, "gauss"),
+    # one-wave workgroups on a launch of more than two waves per SIMD (no prefetch)
+    (1024, 256, 300, 80, 5, 0, "ci16", True, "bpsk"),
     (2048, 65, 5, 7, 25, 11, "c64", True, "phase"),
     (4096, 1000, 4, 9, 25, 0, "ci16", True, "bpsk"),
     (8192, 333, 3, 4, 10, 5, "c64", False, "phase"),
