@@ -158,6 +158,13 @@ __device__ __forceinline__ void dft16_pre1(float2 (&v)[16], const float2 (&w)[16
   dft16_stage_b(v, k);
 }
 
+// 16-point forward DFT of v.
+__device__ __forceinline__ void dft16(float2 (&v)[16], const Dft16Consts& k) {
+#pragma unroll
+  for (int j1 = 0; j1 < 4; ++j1) dft4(v[j1], v[j1 + 4], v[j1 + 8], v[j1 + 12]);
+  dft16_stage_b(v, k);
+}
+
 // 16-point forward DFT of (w[j] v[j]).
 __device__ __forceinline__ void dft16_pre(float2 (&v)[16], const float2 (&w)[16],
                                           const Dft16Consts& k) {
@@ -246,13 +253,18 @@ __device__ __forceinline__ void load_wave_twiddles(WaveTwiddles& w, const float2
 // holds f[l + 64 j] in v[j]; xw is the wave's exchange buffer.  On exit
 // acc[4 t + kd] += |F[kb]|^2 for kb = ka + 16 (4 row + t) + 256 kd, with
 // ka = lane & 15, row = lane >> 4 (F including the bin-class factors).
+// K0: the wave's bin class is 0 (N = 1024), so the pass-1 factors are all 1.
+template <bool K0 = false>
 __device__ __forceinline__ void wave_fft_accumulate(float2 (&v)[16], float2* xw,
                                                     const WaveTwiddles& w,
                                                     const Dft16Consts& dk, float (&acc)[16],
                                                     int lane) {
   const int ka = lane & 15, row = lane >> 4;
   // pass 1: pre-twiddle and 16-point DFT over the stride-64 samples of a lane
-  dft16_pre1(v, w.pre, dk);
+  if constexpr (K0)
+    dft16(v, dk);
+  else
+    dft16_pre1(v, w.pre, dk);
 #pragma unroll
   for (int k = 0; k < 16; ++k) xw[k * XPITCH + lane] = v[k];
   wave_lds_sync();
@@ -320,9 +332,12 @@ __device__ __forceinline__ float* out_row(const FusedArgs& a, int g, int c) {
 // RW waves share a gate and a pulse: the decoded row is staged once in LDS.
 // PF (one-wave workgroups only): fetch the next pulse during this pulse's
 // transform, for launches too small to hide memory latency with other waves
-// (the extra registers cost a wave per SIMD on large launches).
-template <int RW, int ST, bool PF = false>
+// (the extra registers cost a wave per SIMD on large launches).  K0 (one-wave
+// workgroups at N = 1024 only): the single bin class is 0, so pass 1 has no
+// pre-twiddles.
+template <int RW, int ST, bool PF = false, bool K0 = false>
 __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
+  static_assert(!K0 || RW == 1, "bin class 0 alone: one-wave workgroups at N = 1024");
   constexpr int NT = 64 * RW;
   constexpr int E = SUB / NT;          // decoded samples staged per thread
   constexpr bool DBUF = (RW == 16);    // double-buffer the decoded row when LDS allows
@@ -392,7 +407,7 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
         if (p + 1 < p1) load(p + 1);
-        wave_fft_accumulate(v, xw, wt, dk, acc, lane);
+        wave_fft_accumulate<K0>(v, xw, wt, dk, acc, lane);
       }
     } else {
       // the other waves on the SIMD hide the load latency
@@ -401,7 +416,7 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
         float2 v[16];
 #pragma unroll
         for (int j = 0; j < 16; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
-        wave_fft_accumulate(v, xw, wt, dk, acc, lane);
+        wave_fft_accumulate<K0>(v, xw, wt, dk, acc, lane);
       }
     }
   } else {
@@ -698,11 +713,17 @@ hipError_t launch_fused_t(const FusedArgs& a, hipStream_t stream) {
   // one-wave workgroups prefetch when the launch has at most two waves per SIMD
   constexpr int64_t kPrefetchMaxWaves = 2 * 4 * 256;
   if constexpr (RW == 1) {
-    if (blocks <= kPrefetchMaxWaves) {
-      hipLaunchKernelGGL((fused_spectra<1, ST, true>), dim3(static_cast<unsigned>(blocks)),
-                         dim3(64), 0, stream, a);
-      return hipGetLastError();
-    }
+    const bool pf = blocks <= kPrefetchMaxWaves, k0 = a.log2_r == 0;
+    const dim3 grid(static_cast<unsigned>(blocks)), block(64);
+    if (pf && k0)
+      hipLaunchKernelGGL((fused_spectra<1, ST, true, true>), grid, block, 0, stream, a);
+    else if (pf)
+      hipLaunchKernelGGL((fused_spectra<1, ST, true, false>), grid, block, 0, stream, a);
+    else if (k0)
+      hipLaunchKernelGGL((fused_spectra<1, ST, false, true>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((fused_spectra<1, ST, false, false>), grid, block, 0, stream, a);
+    return hipGetLastError();
   }
   hipLaunchKernelGGL((fused_spectra<RW, ST, false>), dim3(static_cast<unsigned>(blocks)),
                      dim3(64 * RW), 0, stream, a);
