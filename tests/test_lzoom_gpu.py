@@ -278,3 +278,37 @@ def test_learned_zoom_rejects_bad_setups(ispl):
     with pytest.raises(ispl.IsplError):
         ispl.LearnedZoom(net, code_len=100, fft_len=16384, window_bins=256, threshold=0.0, **geo)
     net.close()
+
+
+def test_learned_zoom_without_pulses(ispl):
+    """No pulses: every spectrum is zero, the network sees a constant input and
+    is not confident anywhere, every gate falls back to its (zero) full row and
+    reports bin 0 with power 0 -- the plain path's answer for a zero row."""
+    cfg = CONFIGS["zoom"].replace(n_pulses=4)
+    d = make_dataset(cfg, 3, cache_dir=None)
+    G = cfg.n_gates
+    net = ispl.Net(1)
+    net.set_params(cnn.init_params(4).astype(np.float32))
+    lz = ispl.LearnedZoom(net, code_len=cfg.code_len, fft_len=cfg.fft_len, window_bins=256,
+                          n_gates=G, gate_step=cfg.gate_step, pulse_stride=cfg.pulse_stride,
+                          max_pulses=cfg.n_pulses)
+    xs, xt = dev(d.samples), dev(d.tx)
+    bins, power = lz.peaks(xs[:0], xt[:0])
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(bins).item() == 0
+    assert torch.count_nonzero(power).item() == 0
+    v = lz.view()
+    assert v["counts"].cpu().tolist() == [0, G]
+    # a call with pulses afterwards is unaffected by the empty one: it equals a
+    # fresh object's (the decision's completion counter was reset)
+    bins2, power2 = lz.peaks(xs, xt)
+    fresh = ispl.LearnedZoom(net, code_len=cfg.code_len, fft_len=cfg.fft_len, window_bins=256,
+                             n_gates=G, gate_step=cfg.gate_step, pulse_stride=cfg.pulse_stride,
+                             max_pulses=cfg.n_pulses)
+    bins3, power3 = fresh.peaks(xs, xt)
+    torch.cuda.synchronize()
+    assert torch.equal(bins2, bins3) and torch.equal(power2, power3)
+    assert sum(lz.view()["counts"].cpu().tolist()) == G
+    lz.close()
+    fresh.close()
+    net.close()
