@@ -291,8 +291,9 @@ struct ZoomPlan {
 
 // Bins per workgroup: 256 when K allows it (each staged sample feeds twice the
 // matrix work), else 128.  Pulse chunks until there are two workgroups per
-// compute unit, but at least 24 pulses per chunk; one or two 32-pulse column
-// tiles per block (more, with the prefetched samples, would spill).
+// compute unit (two rounds over the chip: one 12-wave workgroup fits a CU), but
+// at least 24 pulses per chunk; one or two 32-pulse column tiles per block
+// (four would not fit the matrix waves' registers).
 ZoomPlan zoom_plan(int32_t n_gates, int32_t n_bins, int32_t n_pulses) {
   ZoomPlan z{};
   z.rt = n_bins % 256 == 0 ? 2 : 1;
