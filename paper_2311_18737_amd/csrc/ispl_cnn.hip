@@ -420,12 +420,17 @@ __device__ __forceinline__ void store_tile(const nf32x16& acc, const float (&bv)
   }
 }
 
-// Forward workgroup: FW_WAVES waves, each owning FW_SPAN consecutive positions.
-constexpr int FW_WAVES = 8;
+// Forward workgroup: FW_WAVES waves, each owning FW_SPAN consecutive positions
+// of the matrix-core layers.  The input stage (features) runs on the first
+// FW_IN_THREADS threads, two positions each, whatever FW_WAVES is, so its
+// reduction order (and hence every result) does not depend on the tiling.
+constexpr int FW_WAVES = 16;
 constexpr int FW_THREADS = 64 * FW_WAVES;
-constexpr int FW_SPAN = T / FW_WAVES;   // 128 positions per wave
+constexpr int FW_SPAN = T / FW_WAVES;   // 64 positions per wave
 constexpr int FW_PAIRS = FW_SPAN / 64;  // pairs of 32-position tiles per wave
 constexpr int FW_PER_THREAD = T / FW_THREADS;
+constexpr int FW_IN_THREADS = T / 2;
+constexpr int FW_IN_WAVES = FW_IN_THREADS / 64;
 static_assert(FW_SPAN % 64 == 0 && T % FW_THREADS == 0, "forward tiling");
 
 // One 32-channel layer: each wave sweeps its positions as pairs of
@@ -489,15 +494,17 @@ __global__ void __launch_bounds__(FW_THREADS) net_forward_bf16(const float* __re
   __shared__ __attribute__((aligned(16))) float xs[T];
   __shared__ __attribute__((aligned(16))) uint16_t act0[T * 32];
   __shared__ __attribute__((aligned(16))) uint16_t act1[T * 32];
-  __shared__ float red[FW_WAVES];
+  __shared__ float red[FW_IN_WAVES];
   __shared__ float w4s[32 * TAPS];  // layer-4 weights, read by every lane
   const int g = blockIdx.x, j = threadIdx.x, lane = j & 63;
   const int wave = __builtin_amdgcn_readfirstlane(j >> 6);
   const int h = lane >> 5, c = lane & 31;
   if (j < 32 * TAPS) w4s[j] = nw->w4[j];
-  static_assert(FW_PER_THREAD == 2, "two input values per thread");
-  float2 v;
-  if (FROM_SPECTRA && chunks > 1) {
+  // input stage: thread j < FW_IN_THREADS holds positions 2 j, 2 j + 1
+  const bool in = j < FW_IN_THREADS;  // whole waves
+  float2 v = make_float2(0.f, 0.f);
+  if (!in) {
+  } else if (FROM_SPECTRA && chunks > 1) {
     const int64_t cs = static_cast<int64_t>(gridDim.x) * T;
     const float2* pr = reinterpret_cast<const float2*>(partial + static_cast<int64_t>(g) * T) + j;
     v = make_float2(0.f, 0.f);
@@ -519,18 +526,20 @@ __global__ void __launch_bounds__(FW_THREADS) net_forward_bf16(const float* __re
     v = reinterpret_cast<const float2*>(x + static_cast<int64_t>(g) * T)[j];
   }
   if (FROM_SPECTRA) {
-    float sum = v.x + v.y;
+    if (in) {
+      float sum = v.x + v.y;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-    if (lane == 0) red[wave] = sum;
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+      if (lane == 0) red[wave] = sum;
+    }
     __syncthreads();
     float tot = 0.f;
 #pragma unroll
-    for (int w = 0; w < FW_WAVES; ++w) tot += red[w];  // fixed order
+    for (int w = 0; w < FW_IN_WAVES; ++w) tot += red[w];  // fixed order
     const float inv = 1.f / (tot / static_cast<float>(T));
     v = make_float2(logf(fmaxf(v.x * inv, 1e-30f)), logf(fmaxf(v.y * inv, 1e-30f)));
   }
-  reinterpret_cast<float2*>(xs)[j] = v;
+  if (in) reinterpret_cast<float2*>(xs)[j] = v;
   __syncthreads();
   // layer 1: one k-step, B[k][t] = bf16(x[t + k - 3]) for k < 7 (lanes h = 1 hold k >= 8: zero)
   {
