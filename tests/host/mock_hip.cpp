@@ -8,6 +8,7 @@
 // graph, a capture on a capturing stream are all counted as errors).
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cassert>
 #include <cstdio>
 #include <cstdlib>
@@ -23,24 +24,34 @@
 static std::map<uintptr_t, size_t> g_allocs;
 static int g_errors = 0;
 
-static void check_range(const void* p, size_t bytes, const char* what) {
-  if (bytes == 0) return;
+static bool check_range(const void* p, size_t bytes, const char* what) {
+  if (bytes == 0) return true;
   uintptr_t a = reinterpret_cast<uintptr_t>(p);
   auto it = g_allocs.upper_bound(a);
   if (it == g_allocs.begin()) {
     fprintf(stderr, "MOCK OOB: %s %p (+%zu) not in any allocation\n", what, p, bytes);
     ++g_errors;
-    return;
+    return false;
   }
   --it;
   if (a < it->first || a + bytes > it->first + it->second) {
     fprintf(stderr, "MOCK OOB: %s %p +%zu outside [%p, +%zu)\n", what, p, bytes,
             reinterpret_cast<void*>(it->first), it->second);
     ++g_errors;
+    return false;
   }
+  return true;
+}
+
+static void mock_fail(const char* what) {
+  fprintf(stderr, "MOCK: %s\n", what);
+  ++g_errors;
 }
 
 int mock_errors() { return g_errors; }
+
+static long g_ops = 0;  // stream operations executed (eagerly or by a graph replay)
+long mock_ops() { return g_ops; }
 
 struct MStream;
 struct MGraph {
@@ -81,10 +92,14 @@ static MStream* S(hipStream_t s) {
 // Records an operation on a stream: executed now, or captured into the graph.
 static void run_on(hipStream_t s, std::function<void()> op) {
   MStream* m = S(s);
-  if (m->capture) {
-    m->graph->ops.push_back(op);
-  } else {
+  auto counted = [op] {
+    ++g_ops;
     op();
+  };
+  if (m->capture) {
+    m->graph->ops.push_back(counted);
+  } else {
+    counted();
   }
 }
 
@@ -130,7 +145,7 @@ hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind k) {
   return hipSuccess;
 }
 hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind k, hipStream_t st) {
-  run_on(st, [=] { hipMemcpy(d, s, n, k); });
+  run_on(st, [=] { (void)hipMemcpy(d, s, n, k); });
   return hipSuccess;
 }
 hipError_t hipMemcpy2DAsync(void* d, size_t dp, const void* s, size_t sp, size_t w, size_t h,
@@ -285,6 +300,50 @@ hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s) {
 
 namespace ispl {
 
+// The gates a launch works on: all of them, or list[i] for i < min(*count, cap)
+// inside [0, G) (the kernels skip other entries).
+static std::vector<int> active_gates(const int32_t* list, const int32_t* count, int G, int cap) {
+  std::vector<int> gs;
+  if (!list) {
+    for (int g = 0; g < G; ++g) gs.push_back(g);
+    return gs;
+  }
+  if (!check_range(count, 4, "gate count")) return gs;
+  const int n = std::min(std::max(*count, 0), cap);
+  if (!check_range(list, size_t(n) * 4, "gate list")) return gs;
+  for (int i = 0; i < n; ++i)
+    if (list[i] >= 0 && list[i] < G) gs.push_back(list[i]);
+  return gs;
+}
+
+// Rows [p][first + g step, + len) of pulses p < P for the gates gs.
+static void check_windows(const void* samples, size_t ss, int64_t stride, int64_t first,
+                          int64_t step, int64_t len, int P, const std::vector<int>& gs,
+                          const char* what) {
+  if (P < 1) return;
+  for (int g : gs) {
+    const int64_t last = int64_t(P - 1) * stride + first + g * step + len;
+    check_range(samples, size_t(last) * ss, what);
+  }
+}
+
+static void check_rows(const void* base, int64_t row_len, const std::vector<int>& gs,
+                       const char* what) {
+  for (int g : gs)
+    check_range(static_cast<const float*>(base) + g * row_len, size_t(row_len) * 4, what);
+}
+
+static void check_pulse_exponents(const void* samples, int st, const float* tx, int64_t stride,
+                                  int64_t lo, int64_t hi, int L, int per_pulse, int P,
+                                  const int32_t* exps) {
+  if (P < 1) return;
+  if (lo < 0 || hi < lo || hi > stride) mock_fail("pulse exponents: span outside the row");
+  check_range(samples, size_t(int64_t(P - 1) * stride + hi) * (st == 1 ? 4 : 8), "exp samples");
+  check_range(tx, size_t(per_pulse ? P : 1) * L * 8, "exp tx");
+  check_range(exps, size_t(P) * 4, "exp out");
+}
+
+
 int fused_lds_bytes(int rw, int sub_len) {
   const int XWAVE = 16 * 65;
   if (sub_len == 16 * SUB) return 8 * 16 * XWAVE;
@@ -303,22 +362,28 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t st) {
         fprintf(stderr, "MOCK: fused rw %d with R %d\n", c.waves_per_block, R); ++g_errors;
       }
     }
+    const std::vector<int> gs = active_gates(c.gate_list, c.gate_count, c.n_gates, c.n_gates);
     if (c.n_pulses > 0) {
-      const int64_t last = int64_t(c.n_pulses - 1) * c.stride + c.first_gate +
-                           int64_t(c.n_gates - 1) * c.gate_step + c.code_len;
-      check_range(c.samples, size_t(last) * ss, "fused samples");
+      check_windows(c.samples, ss, c.stride, c.first_gate, c.gate_step, c.code_len, c.n_pulses,
+                    gs, "fused samples");
       check_range(c.tx, size_t(c.tx_per_pulse ? c.n_pulses : 1) * c.code_len * 8, "fused tx");
     }
+    if (c.chunks < 1) mock_fail("fused: no pulse chunk");
     check_range(c.twiddle, size_t(c.n_fft) * 8, "fused twiddle");
-    check_range(c.out, size_t(c.chunks) * c.n_gates * c.n_fft * 4, "fused out");
+    for (int k = 0; k < c.chunks; ++k)
+      check_rows(c.out + int64_t(k) * c.n_gates * c.n_fft, c.n_fft, gs, "fused out");
   });
   return hipSuccess;
 }
 hipError_t launch_reduce_chunks(const float* partial, float* spectra, int64_t elems, int32_t chunks,
-                                int32_t, int32_t, const int32_t*, const int32_t*, hipStream_t st) {
+                                int32_t, int32_t n_fft, const int32_t* list, const int32_t* count,
+                                hipStream_t st) {
   run_on(st, [=] {
-    check_range(partial, size_t(chunks) * elems * 4, "reduce partial");
-    check_range(spectra, size_t(elems) * 4, "reduce spectra");
+    if (n_fft < 1 || elems % n_fft != 0) mock_fail("reduce: elems not whole rows");
+    const int G = static_cast<int>(elems / n_fft);
+    const std::vector<int> gs = active_gates(list, count, G, G);
+    for (int k = 0; k < chunks; ++k) check_rows(partial + k * elems, n_fft, gs, "reduce partial");
+    check_rows(spectra, n_fft, gs, "reduce spectra");
   });
   return hipSuccess;
 }
@@ -326,23 +391,244 @@ hipError_t launch_fill_zero(float* dst, int64_t elems, hipStream_t st) {
   run_on(st, [=] { check_range(dst, size_t(elems) * 4, "fill_zero"); });
   return hipSuccess;
 }
-hipError_t launch_fill_zero_rows(float* dst, int32_t g, int32_t n, const int32_t*, const int32_t*,
-                                 hipStream_t st) {
-  run_on(st, [=] { check_range(dst, size_t(g) * n * 4, "fill_zero_rows"); });
+hipError_t launch_fill_zero_rows(float* dst, int32_t g, int32_t n, const int32_t* list,
+                                 const int32_t* count, hipStream_t st) {
+  run_on(st, [=] { check_rows(dst, n, active_gates(list, count, g, g), "fill_zero_rows"); });
   return hipSuccess;
 }
-hipError_t launch_zoom(const ZoomArgs&, hipStream_t, bool) { return hipSuccess; }
-hipError_t launch_net_features(const float*, int, float*, hipStream_t) { return hipSuccess; }
-hipError_t launch_net_forward_f32(const NetWork&, const float*, int, float*, hipStream_t) { return hipSuccess; }
-hipError_t launch_net_loss_grad(const NetWork&, const float*, const float*, int, float*, float*, hipStream_t) { return hipSuccess; }
+hipError_t launch_zoom(const ZoomArgs& a, hipStream_t st, bool exponents) {
+  ZoomArgs c = a;
+  run_on(st, [c, exponents] {
+    if (c.n_pulses < 1) {
+      mock_fail("zoom launch without pulses (an empty grid)");
+      return;
+    }
+    if ((c.row_tiles != 1 && c.row_tiles != 2) || (c.col_tiles != 1 && c.col_tiles != 2) ||
+        c.n_bins % (128 * c.row_tiles) != 0 || c.code_pad % 64 != 0 || c.code_pad < c.code_len ||
+        c.chunks < 1 || (c.n_fft & (c.n_fft - 1)) != 0)
+      mock_fail("zoom geometry");
+    if (c.precision == 1) {
+      if (exponents)
+        check_pulse_exponents(c.samples, c.sample_type, c.tx, c.stride, c.row_lo, c.row_hi,
+                              c.code_len, c.tx_per_pulse, c.n_pulses, c.col_exp);
+      check_range(c.col_exp, size_t(c.n_pulses) * 4, "zoom col_exp");
+    }
+    const std::vector<int> gs = active_gates(c.gate_list, c.gate_count, c.n_gates, c.n_gates);
+    check_windows(c.samples, c.sample_type == 1 ? 4 : 8, c.stride, c.first_gate, c.gate_step,
+                  c.code_len, c.n_pulses, gs, "zoom samples");
+    check_range(c.tx, size_t(c.tx_per_pulse ? c.n_pulses : 1) * c.code_len * 8, "zoom tx");
+    check_range(c.twiddle, size_t(c.n_fft) * 8, "zoom twiddle");
+    const size_t table = size_t(c.n_bins / 16) * (c.code_pad / 8) * 64 * 16;
+    check_range(c.a_hi, table, "zoom table hi");
+    check_range(c.a_lo, table, "zoom table lo");
+    for (int g : gs) check_range(c.bin_start + g, 4, "zoom bin_start");
+    if (c.chunks == 1) {
+      check_rows(c.out, c.n_bins, gs, "zoom out");
+    } else {
+      for (int k = 0; k < c.chunks; ++k)
+        check_rows(c.partial + int64_t(k) * c.n_gates * c.n_bins, c.n_bins, gs, "zoom partial");
+    }
+  });
+  return hipSuccess;
+}
+
+constexpr int64_t T_NET = NET_LEN;
+
+hipError_t launch_net_features(const float* spectra, int rows, float* out, hipStream_t st) {
+  run_on(st, [=] {
+    if (rows < 1) mock_fail("features launch with an empty grid");
+    check_range(spectra, size_t(rows) * T_NET * 4, "features in");
+    check_range(out, size_t(rows) * T_NET * 4, "features out");
+  });
+  return hipSuccess;
+}
+
+static void check_f32_forward(const NetWork& w, const float* x, int B, const float* logits) {
+  if (B < 1) mock_fail("FP32 forward with an empty grid");
+  check_range(x, size_t(B) * T_NET * 4, "forward x");
+  check_range(w.params, size_t(NET_PARAMS) * 4, "forward params");
+  for (const float* a : {w.a1, w.a2, w.a3}) check_range(a, size_t(B) * 32 * T_NET * 4, "forward act");
+  check_range(logits, size_t(B) * T_NET * 4, "forward logits");
+}
+
+hipError_t launch_net_forward_f32(const NetWork& w, const float* x, int batch, float* logits,
+                                  hipStream_t st) {
+  NetWork c = w;
+  run_on(st, [=] { check_f32_forward(c, x, batch, logits); });
+  return hipSuccess;
+}
+
+hipError_t launch_net_loss_grad(const NetWork& w, const float* x, const float* target_pos,
+                                int batch, float* grad, float* loss_mean, hipStream_t st) {
+  NetWork c = w;
+  run_on(st, [=] {
+    const size_t B = size_t(batch);
+    check_f32_forward(c, x, batch, c.logits);
+    check_range(target_pos, B * 4, "loss target");
+    check_range(c.dz4, B * T_NET * 4, "loss dz4");
+    check_range(c.loss, B * 4, "loss rows");
+    check_range(c.dzA, B * 32 * T_NET * 4, "loss dzA");
+    check_range(c.dzB, B * 32 * T_NET * 4, "loss dzB");
+    check_range(c.part, B * NET_PARAMS * 4, "loss part");
+    check_range(grad, size_t(NET_PARAMS) * 4, "loss grad");
+    check_range(loss_mean, 4, "loss mean");
+  });
+  return hipSuccess;
+}
+
 size_t net_bf16_bytes() { return 65536; }
-hipError_t launch_net_prep_bf16(const float*, void*, hipStream_t) { return hipSuccess; }
-hipError_t launch_net_forward_bf16(const void*, const float*, int, float*, hipStream_t, bool, const float*, int32_t, float*) { return hipSuccess; }
-hipError_t launch_adam(float*, const float*, float*, float*, int, float, int, hipStream_t) { return hipSuccess; }
-hipError_t launch_peak(const float*, int32_t, int32_t, int32_t, int32_t, int32_t*, float*, const int32_t*, const int32_t*, hipStream_t) { return hipSuccess; }
-hipError_t launch_select_windows(const float*, int32_t, int32_t, int32_t, float, int32_t*, float*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, hipStream_t) { return hipSuccess; }
-hipError_t launch_split_peaks(float*, const float*, int32_t, float*, const float*, int32_t, const int32_t*, const int32_t*, int32_t, int32_t, int32_t, int32_t*, float*, hipStream_t) { return hipSuccess; }
-hipError_t launch_select_and_exponents(const float*, int32_t, int32_t, int32_t, float, int32_t*, float*, int32_t*, int32_t*, int32_t*, int32_t*, int32_t*, const PulseExpArgs&, hipStream_t) { return hipSuccess; }
-hipError_t launch_window_peak(const float*, int32_t, int32_t, int32_t, const int32_t*, const int32_t*, const int32_t*, int32_t*, float*, hipStream_t) { return hipSuccess; }
+
+hipError_t launch_net_prep_bf16(const float* params, void* table, hipStream_t st) {
+  run_on(st, [=] {
+    check_range(params, size_t(NET_PARAMS) * 4, "prep params");
+    check_range(table, net_bf16_bytes(), "prep table");
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_net_forward_bf16(const void* table, const float* x, int batch, float* logits,
+                                   hipStream_t st, bool from_spectra, const float* partial,
+                                   int32_t chunks, float* x_out) {
+  run_on(st, [=] {
+    const size_t B = size_t(batch);
+    if (batch < 1) mock_fail("BF16 forward with an empty grid");
+    check_range(table, net_bf16_bytes(), "bf16 table");
+    if (from_spectra && chunks > 1) {
+      check_range(partial, size_t(chunks) * B * T_NET * 4, "bf16 partial");
+      check_range(x_out, B * T_NET * 4, "bf16 x_out");
+    } else {
+      check_range(x, B * T_NET * 4, "bf16 x");
+    }
+    check_range(logits, B * T_NET * 4, "bf16 logits");
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_adam(float* params, const float* grad, float* m, float* v, int n, float, int,
+                       hipStream_t st) {
+  run_on(st, [=] {
+    for (const float* p : {static_cast<const float*>(params), grad, static_cast<const float*>(m),
+                           static_cast<const float*>(v)})
+      check_range(p, size_t(n) * 4, "adam");
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_peak(const float* spectra, int32_t n_gates, int32_t n_fft, int32_t bin_lo,
+                       int32_t bin_hi, int32_t* peak_bin, float* peak_power, const int32_t* list,
+                       const int32_t* count, hipStream_t st) {
+  run_on(st, [=] {
+    if (n_gates < 1) mock_fail("peak launch with an empty grid");
+    if (bin_lo < 0 || bin_lo >= n_fft || bin_hi < 1 || bin_hi > n_fft || bin_lo == bin_hi)
+      mock_fail("peak band");
+    const std::vector<int> gs = active_gates(list, count, n_gates, n_gates);
+    check_rows(spectra, n_fft, gs, "peak spectra");
+    check_rows(peak_bin, 1, gs, "peak bin");
+    if (peak_power) check_rows(peak_power, 1, gs, "peak power");
+  });
+  return hipSuccess;
+}
+
+// The window decision's outputs, written the way the kernel writes them (a
+// fixed pattern of zoomed gates stands in for the network's confidence).
+static void emulate_select(const float* logits, int32_t G, int32_t fine_len, int32_t K,
+                           int32_t* bin_start, float* confidence, int32_t* flag,
+                           int32_t* zoom_list, int32_t* fallback_list, int32_t* counts,
+                           int32_t* done) {
+  if (G < 1) mock_fail("select launch with an empty grid");
+  if (fine_len < T_NET || fine_len % T_NET != 0 || K < 1 || K > fine_len)
+    mock_fail("select window geometry");
+  bool ok = check_range(logits, size_t(G) * T_NET * 4, "select logits");
+  for (const void* p : {static_cast<const void*>(bin_start), static_cast<const void*>(flag),
+                        static_cast<const void*>(zoom_list), static_cast<const void*>(fallback_list)})
+    ok = check_range(p, size_t(G) * 4, "select per-gate output") && ok;
+  if (confidence) ok = check_range(confidence, size_t(G) * 4, "select confidence") && ok;
+  ok = check_range(counts, 8, "select counts") && ok;
+  ok = check_range(done, 4, "select done") && ok;
+  if (!ok) return;
+  if (*done != 0) mock_fail("select: completion counter not zero at the start of a call");
+  int nz = 0;
+  for (int g = 0; g < G; ++g) {
+    const bool z = (g * 7 + 3) % 5 != 0;
+    flag[g] = z ? 1 : 0;
+    bin_start[g] = static_cast<int32_t>((int64_t(g) * 997) % fine_len);
+    if (confidence) confidence[g] = z ? 0.95f : 0.5f;
+    if (z)
+      zoom_list[nz++] = g;
+    else
+      fallback_list[g - nz] = g;
+  }
+  counts[0] = nz;
+  counts[1] = G - nz;
+  *done = 0;
+}
+
+hipError_t launch_select_windows(const float* logits, int32_t n_gates, int32_t fine_len,
+                                 int32_t window_bins, float, int32_t* bin_start,
+                                 float* confidence, int32_t* flag, int32_t* zoom_list,
+                                 int32_t* fallback_list, int32_t* counts, int32_t* done,
+                                 hipStream_t st) {
+  run_on(st, [=] {
+    emulate_select(logits, n_gates, fine_len, window_bins, bin_start, confidence, flag, zoom_list,
+                   fallback_list, counts, done);
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int32_t fine_len,
+                                       int32_t window_bins, float, int32_t* bin_start,
+                                       float* confidence, int32_t* flag, int32_t* zoom_list,
+                                       int32_t* fallback_list, int32_t* counts, int32_t* done,
+                                       const PulseExpArgs& pe, hipStream_t st) {
+  PulseExpArgs e = pe;
+  run_on(st, [=] {
+    emulate_select(logits, n_gates, fine_len, window_bins, bin_start, confidence, flag, zoom_list,
+                   fallback_list, counts, done);
+    if (e.n_pulses < 0) mock_fail("negative pulse count");
+    check_pulse_exponents(e.samples, e.sample_type, e.tx, e.stride, e.lo, e.hi, e.code_len,
+                          e.tx_per_pulse, e.n_pulses, e.exps);
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_split_peaks(float* window_spectra, const float* window_partial,
+                              int32_t zoom_chunks, float* full_spectra, const float* full_partial,
+                              int32_t fine_chunks, const int32_t* flag, const int32_t* bin_start,
+                              int32_t n_gates, int32_t window_bins, int32_t fine_len,
+                              int32_t* peak_bin, float* peak_power, hipStream_t st) {
+  run_on(st, [=] {
+    if (n_gates < 1) mock_fail("split peaks with an empty grid");
+    if (!check_range(flag, size_t(n_gates) * 4, "split flag")) return;
+    for (int g = 0; g < n_gates; ++g) {
+      const bool z = flag[g] != 0;
+      const int64_t len = z ? window_bins : fine_len;
+      const int chunks = z ? zoom_chunks : fine_chunks;
+      const float* part = z ? window_partial : full_partial;
+      check_range((z ? window_spectra : full_spectra) + g * len, size_t(len) * 4, "split row");
+      if (chunks > 1)
+        for (int k = 0; k < chunks; ++k)
+          check_range(part + (int64_t(k) * n_gates + g) * len, size_t(len) * 4, "split partial");
+      if (z) check_range(bin_start + g, 4, "split bin_start");
+    }
+    check_range(peak_bin, size_t(n_gates) * 4, "split peak bin");
+    if (peak_power) check_range(peak_power, size_t(n_gates) * 4, "split peak power");
+  });
+  return hipSuccess;
+}
+
+hipError_t launch_window_peak(const float* spectra, int32_t n_gates, int32_t window_bins,
+                              int32_t, const int32_t* bin_start, const int32_t* list,
+                              const int32_t* count, int32_t* peak_bin, float* peak_power,
+                              hipStream_t st) {
+  run_on(st, [=] {
+    if (n_gates < 1) mock_fail("window peak with an empty grid");
+    const std::vector<int> gs = active_gates(list, count, n_gates, n_gates);
+    check_rows(spectra, window_bins, gs, "window peak spectra");
+    check_rows(bin_start, 1, gs, "window peak bin_start");
+    check_rows(peak_bin, 1, gs, "window peak bin");
+    if (peak_power) check_rows(peak_power, 1, gs, "window peak power");
+  });
+  return hipSuccess;
+}
 
 }  // namespace ispl
