@@ -32,6 +32,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ispl_device.h"
 #include "ispl_internal.h"
 
@@ -88,28 +90,60 @@ __device__ __forceinline__ f32x16 mfma(const Frag& a, const Frag& b, f32x16 c) {
                                                   __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
+// Raw form of one sample as fetched: complex64, or the int16 pair in one dword
+// (converted when the chunk is stored, so a fetched chunk holds fewer registers).
 template <int ST>
-__device__ __forceinline__ float2 load_sample(const void* base, int64_t i) {
-  if constexpr (ST == 0) {
-    return reinterpret_cast<const float2*>(base)[i];
-  } else {
-    const uint32_t r = reinterpret_cast<const uint32_t*>(base)[i];
-    return make_float2(static_cast<float>(static_cast<int16_t>(r & 0xffffu)),
-                       static_cast<float>(static_cast<int32_t>(r) >> 16));
-  }
+struct RawSample {
+  using type = float2;
+};
+template <>
+struct RawSample<1> {
+  using type = uint32_t;
+};
+
+template <int ST>
+__device__ __forceinline__ typename RawSample<ST>::type load_raw(const void* base, int64_t i) {
+  return reinterpret_cast<const typename RawSample<ST>::type*>(base)[i];
+}
+// Four consecutive elements from element i of a row, as one access.
+struct alignas(4) Dword4 {
+  uint32_t v[4];
+};
+struct alignas(8) Complex4 {
+  float2 v[4];
+};
+__device__ __forceinline__ void load4(const void* base, int64_t i, uint32_t (&out)[4]) {
+  const Dword4 q = *reinterpret_cast<const Dword4*>(static_cast<const uint32_t*>(base) + i);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = q.v[k];
+}
+__device__ __forceinline__ void load4(const void* base, int64_t i, float2 (&out)[4]) {
+  const Complex4 q = *reinterpret_cast<const Complex4*>(static_cast<const float2*>(base) + i);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) out[k] = q.v[k];
+}
+__device__ __forceinline__ float2 to_complex(float2 x) { return x; }
+__device__ __forceinline__ float2 to_complex(uint32_t r) {
+  return make_float2(static_cast<float>(static_cast<int16_t>(r & 0xffffu)),
+                     static_cast<float>(static_cast<int32_t>(r) >> 16));
 }
 
-// One 64-sample chunk of the B operand.  A building thread owns items (column
-// pc, group qg of 4 consecutive samples) with qg = thread % 16 fixed and pc =
-// thread / 16 + CS i, so the 16 lanes of one column read one contiguous run of
-// the pulse row (and of its code).  load_chunk fetches the samples, codes and
-// shift twiddles (indices clamped into the row, so every load is valid);
-// store_chunk zeroes samples past L and pulses past the chunk, decodes,
-// shifts, scales and splits them into high and low halves and stores them in
-// the MFMA B layout (k-step qg / 2, lane half qg % 2).
-template <int NI>
+// One fetched 64-sample chunk of the B operand.  A building thread owns items
+// (column pc, group qg of 4 consecutive samples) with qg = thread % 16 fixed
+// and pc = thread / 16 + 16 i, so the 16 lanes of one column read one
+// contiguous run of the pulse row (and of its code).  fetch_chunk loads the
+// samples, codes, shift twiddles (the same for every column) and the FP16
+// column scales, with indices clamped into the row and pulses past the
+// workgroup's range replaced by its first one, so every load is valid and
+// unconditional; put_chunk zeroes samples past L and pulses past the range,
+// decodes, shifts, scales and splits them into high and low halves and stores
+// them in the MFMA B layout (k-step qg / 2, lane half qg % 2).
+template <int ST, int NI>
 struct ChunkRegs {
-  float2 x[NI][4], c[NI][4], w[NI][4];
+  typename RawSample<ST>::type x[NI][4];
+  float2 c[NI][4];
+  float2 w[4];
+  float scale[NI];
 };
 
 // Column pc's B fragment of k-step ks sits at slot lane ^ swz(ks, lane) of the
@@ -117,51 +151,74 @@ struct ChunkRegs {
 // spreads the 16 lanes of one column's store over 16 bank groups.
 __device__ __forceinline__ int b_slot(int ks, int ln) { return ln ^ ((2 * ks + (ln >> 5)) & 15); }
 
-struct ItemCtx {
-  int64_t rowp;        // sample index of the gate window in this item's pulse row
-  const float2* txp;   // code row of this item's pulse
-  bool live;           // pulse inside the chunk
-};
-
-template <int ST, int NI>
-__device__ __forceinline__ void load_chunk(const ZoomArgs& a, ChunkRegs<NI>& r, int ch, int qg,
-                                           const ItemCtx (&it)[NI], uint32_t k0) {
+// Fetches chunk ch of pulse block pb (columns pb + pc0 + 16 i < p1 are live).
+template <int PREC, int ST, int NI, bool VEC>
+__device__ __forceinline__ void fetch_chunk(const ZoomArgs& a, ChunkRegs<ST, NI>& r, int pb,
+                                            int ch, int pc0, int qg, int p0, int p1,
+                                            int64_t gate_off, uint32_t k0) {
   const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
+  const float2* __restrict__ txb = reinterpret_cast<const float2*>(a.tx);
   const uint32_t nmask = static_cast<uint32_t>(a.n_fft - 1);
   const int L = a.code_len;
 #pragma unroll
-  for (int i = 0; i < NI; ++i)
-#pragma unroll
-    for (int s2 = 0; s2 < 4; ++s2) {
-      const int n = ch * ZCHUNK + 4 * qg + s2;
-      const int ne = n < L ? n : L - 1;  // always inside the row
-      r.x[i][s2] = load_sample<ST>(a.samples, it[i].rowp + ne);
-      r.c[i][s2] = it[i].txp[ne];
-      // N is a power of two, so k0 n mod N survives the 32-bit wrap
-      r.w[i][s2] = tw[(k0 * static_cast<uint32_t>(ne)) & nmask];
-    }
-}
-
-// Item i of the thread is column pc0 + CS i.
-template <int PREC, int NI, int CS>
-__device__ __forceinline__ void store_chunk(const ChunkRegs<NI>& r, Frag (*bh)[ZKS][64],
-                                            Frag (*bl)[ZKS][64], int pc0, int qg,
-                                            const float (&scale)[NI], const ItemCtx (&it)[NI],
-                                            int ch, int L) {
+  for (int s2 = 0; s2 < 4; ++s2) {
+    const int n = ch * ZCHUNK + 4 * qg + s2;
+    const int ne = n < L ? n : L - 1;  // always inside the row
+    // N is a power of two, so k0 n mod N survives the 32-bit wrap
+    r.w[s2] = tw[(k0 * static_cast<uint32_t>(ne)) & nmask];
+  }
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
-    const int pc = pc0 + CS * i;
+    const int p = pb + pc0 + 16 * i;
+    const int pr = p < p1 ? p : p0;
+    const int64_t rowp = static_cast<int64_t>(pr) * a.stride + gate_off;
+    const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(pr) * L : 0);
+    if constexpr (PREC == 1) {
+      const int e = a.col_exp[pr];
+      r.scale[i] = p < p1 ? ldexpf(1.f, e) : 1.f;
+    } else {
+      r.scale[i] = 1.f;
+    }
+    if constexpr (VEC) {
+      // L % 4 == 0, so a group lies wholly inside [0, L) or wholly past it;
+      // groups past it fetch the row's last four samples (zeroed when stored)
+      const int nq = ch * ZCHUNK + 4 * qg;
+      const int n0 = nq < L ? nq : L - 4;
+      load4(a.samples, rowp + n0, r.x[i]);
+      load4(txp, n0, r.c[i]);
+    } else {
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) {
+        const int n = ch * ZCHUNK + 4 * qg + s2;
+        const int ne = n < L ? n : L - 1;
+        r.x[i][s2] = load_raw<ST>(a.samples, rowp + ne);
+        r.c[i][s2] = txp[ne];
+      }
+    }
+  }
+}
+
+// Stores a fetched chunk (see fetch_chunk) into one LDS B buffer.
+template <int PREC, int ST, int NI>
+__device__ __forceinline__ void put_chunk(const ChunkRegs<ST, NI>& r, Frag (*bh)[ZKS][64],
+                                          Frag (*bl)[ZKS][64], int pb, int ch, int pc0, int qg,
+                                          int p1, int L) {
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int pc = pc0 + 16 * i;
+    const bool live = pb + pc < p1;
     Frag fh, fl;
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
-      // samples past L and pulses past the chunk contribute zero
-      const bool keep = it[i].live && ch * ZCHUNK + 4 * qg + s2 < L;
-      const float2 x = keep ? r.x[i][s2] : make_float2(0.f, 0.f);
+      // samples past L and pulses past the range contribute zero
+      const bool keep = live && ch * ZCHUNK + 4 * qg + s2 < L;
+      const float2 xr = to_complex(r.x[i][s2]);
+      const float2 x = keep ? xr : make_float2(0.f, 0.f);
       const float2 c = keep ? r.c[i][s2] : make_float2(0.f, 0.f);
-      const float2 w = r.w[i][s2];
+      const float2 w = r.w[s2];
       const float2 d = make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
-      const float2 y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * scale[i],
-                                   fmaf(d.x, w.y, d.y * w.x) * scale[i]);
+      const float2 y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * r.scale[i],
+                                   fmaf(d.x, w.y, d.y * w.x) * r.scale[i]);
       uint32_t rh, rl, ih, il;
       split2<PREC>(y.x, rh, rl);
       split2<PREC>(y.y, ih, il);
@@ -227,39 +284,33 @@ __global__ void __launch_bounds__(ZTA) zoom_spectra(ZoomArgs a) {
 
   if (wave >= ZW) {
     // ---- building waves ----
+    // Chunks in the matrix waves' order, each fetched and stored between two
+    // barriers.  Per pulse block both roles pass one barrier after each
+    // stored chunk and one more at the block's end.
     const uint32_t k0 = static_cast<uint32_t>(((a.bin_start[g] % N) + N) % N);
-    const float2* __restrict__ txb = reinterpret_cast<const float2*>(a.tx);
     const int64_t gate_off =
         static_cast<int64_t>(a.first_gate) + static_cast<int64_t>(g) * a.gate_step;
     const int bt_id = tid - 64 * ZW;
     const int qg = bt_id & 15, pc0 = bt_id >> 4;
     static_assert(64 * ZP / 16 * NI == NCOL, "items cover the block's columns");
-    for (int pb = p0; pb < p1; pb += NCOL) {
-      ItemCtx it[NI];
-      float scale[NI];
-#pragma unroll
-      for (int i = 0; i < NI; ++i) {
-        const int p = pb + pc0 + 16 * i;
-        const bool live = p < p1;
-        const int pr = live ? p : p0;
-        it[i].rowp = static_cast<int64_t>(pr) * a.stride + gate_off;
-        it[i].txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(pr) * L : 0);
-        it[i].live = live;
-        scale[i] = (PREC == 1 && live) ? ldexpf(1.f, a.col_exp[p]) : 1.f;
-      }
-      ChunkRegs<NI> cr;
-      load_chunk<ST, NI>(a, cr, 0, qg, it, k0);
-      store_chunk<PREC, NI, 16>(cr, bh[0], bl[0], pc0, qg, scale, it, 0, L);
-      __syncthreads();
-      for (int ch = 0; ch < nchunks; ++ch) {
-        if (ch + 1 < nchunks) {  // chunk ch + 1 while the matrix waves work on chunk ch
-          load_chunk<ST, NI>(a, cr, ch + 1, qg, it, k0);
-          store_chunk<PREC, NI, 16>(cr, bh[(ch + 1) & 1], bl[(ch + 1) & 1], pc0, qg, scale, it,
-                                    ch + 1, L);
+    // With L a multiple of 4 each group of 4 samples is fetched as one
+    // contiguous 16- or 32-byte run (whole cache lines per instruction).
+    auto build = [&](auto vec) {
+      constexpr bool VEC = decltype(vec)::value;
+      ChunkRegs<ST, NI> r;
+      for (int pb = p0; pb < p1; pb += NCOL) {
+        for (int ch = 0; ch < nchunks; ++ch) {
+          fetch_chunk<PREC, ST, NI, VEC>(a, r, pb, ch, pc0, qg, p0, p1, gate_off, k0);
+          put_chunk<PREC, ST, NI>(r, bh[ch & 1], bl[ch & 1], pb, ch, pc0, qg, p1, L);
+          __syncthreads();
         }
-        __syncthreads();
+        __syncthreads();  // the block's last chunk is consumed
       }
-    }
+    };
+    if (L % 4 == 0)
+      build(std::true_type{});
+    else
+      build(std::false_type{});
     return;
   }
 

@@ -95,6 +95,9 @@ SHAPES = [
     (16384, 1000, 3, 9, 25, 0, "ci16", True, "bpsk", 256),
     (16384, 2000, 2, 4, 25, 5, "c64", True, "phase", 384),
     (65536, 100, 2, 3, 10, 1, "c64", True, "gauss", 128),
+    # L not a multiple of 4 (per-sample fetches with a ragged tail), and L = 4
+    (4096, 301, 3, 40, 13, 2, "ci16", True, "bpsk", 128),
+    (2048, 4, 3, 5, 3, 0, "c64", True, "gauss", 128),
 ]
 
 
