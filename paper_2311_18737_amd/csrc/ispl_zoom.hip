@@ -132,10 +132,11 @@ __device__ __forceinline__ float2 to_complex(uint32_t r) {
 // (column pc, group qg of 4 consecutive samples) with qg = thread % 16 fixed
 // and pc = thread / 16 + 16 i, so the 16 lanes of one column read one
 // contiguous run of the pulse row (and of its code).  fetch_chunk loads the
-// samples, codes, shift twiddles (the same for every column) and the FP16
-// column scales, with indices clamped into the row and pulses past the
-// workgroup's range replaced by its first one, so every load is valid and
-// unconditional; put_chunk zeroes samples past L and pulses past the range,
+// samples, codes and shift twiddles (the same for every column), with indices
+// clamped into the row and pulses past the workgroup's range replaced by its
+// first one, so every load is valid and unconditional; the FP16 column scales
+// are read once per pulse block, so that no wait for them sits between a
+// chunk's loads; put_chunk zeroes samples past L and pulses past the range,
 // decodes, shifts, scales and splits them into high and low halves and stores
 // them in the MFMA B layout (k-step qg / 2, lane half qg % 2).
 template <int ST, int NI>
@@ -143,6 +144,13 @@ struct ChunkRegs {
   typename RawSample<ST>::type x[NI][4];
   float2 c[NI][4];
   float2 w[4];
+};
+
+// Per pulse block: the rows each item reads and its FP16 column scale.
+template <int NI>
+struct BlockItems {
+  int64_t rowp[NI];         // sample index of the gate window in the item's pulse row
+  const float2* txp[NI];    // code row of the item's pulse
   float scale[NI];
 };
 
@@ -151,13 +159,33 @@ struct ChunkRegs {
 // spreads the 16 lanes of one column's store over 16 bank groups.
 __device__ __forceinline__ int b_slot(int ks, int ln) { return ln ^ ((2 * ks + (ln >> 5)) & 15); }
 
-// Fetches chunk ch of pulse block pb (columns pb + pc0 + 16 i < p1 are live).
-template <int PREC, int ST, int NI, bool VEC>
-__device__ __forceinline__ void fetch_chunk(const ZoomArgs& a, ChunkRegs<ST, NI>& r, int pb,
-                                            int ch, int pc0, int qg, int p0, int p1,
-                                            int64_t gate_off, uint32_t k0) {
-  const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
+// Item context of pulse block pb: pulses pb + pc0 + 16 i past p1 read the
+// first pulse of the range instead (valid loads, zeroed when stored).
+template <int PREC, int NI>
+__device__ __forceinline__ void block_items(const ZoomArgs& a, BlockItems<NI>& it, int pb,
+                                            int pc0, int p0, int p1, int64_t gate_off) {
   const float2* __restrict__ txb = reinterpret_cast<const float2*>(a.tx);
+  int e[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    const int p = pb + pc0 + 16 * i;
+    const int pr = p < p1 ? p : p0;
+    it.rowp[i] = static_cast<int64_t>(pr) * a.stride + gate_off;
+    it.txp[i] = txb + (a.tx_per_pulse ? static_cast<int64_t>(pr) * a.code_len : 0);
+    e[i] = PREC == 1 ? a.col_exp[pr] : 0;
+  }
+  __builtin_amdgcn_sched_barrier(0);  // the exponent loads overlap
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+    it.scale[i] = PREC == 1 && pb + pc0 + 16 * i < p1 ? ldexpf(1.f, e[i]) : 1.f;
+}
+
+// Fetches chunk ch for the items of a pulse block.
+template <int ST, int NI, bool VEC>
+__device__ __forceinline__ void fetch_chunk(const ZoomArgs& a, ChunkRegs<ST, NI>& r,
+                                            const BlockItems<NI>& it, int ch, int qg,
+                                            uint32_t k0) {
+  const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
   const uint32_t nmask = static_cast<uint32_t>(a.n_fft - 1);
   const int L = a.code_len;
 #pragma unroll
@@ -169,30 +197,20 @@ __device__ __forceinline__ void fetch_chunk(const ZoomArgs& a, ChunkRegs<ST, NI>
   }
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
-    const int p = pb + pc0 + 16 * i;
-    const int pr = p < p1 ? p : p0;
-    const int64_t rowp = static_cast<int64_t>(pr) * a.stride + gate_off;
-    const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(pr) * L : 0);
-    if constexpr (PREC == 1) {
-      const int e = a.col_exp[pr];
-      r.scale[i] = p < p1 ? ldexpf(1.f, e) : 1.f;
-    } else {
-      r.scale[i] = 1.f;
-    }
     if constexpr (VEC) {
       // L % 4 == 0, so a group lies wholly inside [0, L) or wholly past it;
       // groups past it fetch the row's last four samples (zeroed when stored)
       const int nq = ch * ZCHUNK + 4 * qg;
       const int n0 = nq < L ? nq : L - 4;
-      load4(a.samples, rowp + n0, r.x[i]);
-      load4(txp, n0, r.c[i]);
+      load4(a.samples, it.rowp[i] + n0, r.x[i]);
+      load4(it.txp[i], n0, r.c[i]);
     } else {
 #pragma unroll
       for (int s2 = 0; s2 < 4; ++s2) {
         const int n = ch * ZCHUNK + 4 * qg + s2;
         const int ne = n < L ? n : L - 1;
-        r.x[i][s2] = load_raw<ST>(a.samples, rowp + ne);
-        r.c[i][s2] = txp[ne];
+        r.x[i][s2] = load_raw<ST>(a.samples, it.rowp[i] + ne);
+        r.c[i][s2] = it.txp[i][ne];
       }
     }
   }
@@ -200,9 +218,9 @@ __device__ __forceinline__ void fetch_chunk(const ZoomArgs& a, ChunkRegs<ST, NI>
 
 // Stores a fetched chunk (see fetch_chunk) into one LDS B buffer.
 template <int PREC, int ST, int NI>
-__device__ __forceinline__ void put_chunk(const ChunkRegs<ST, NI>& r, Frag (*bh)[ZKS][64],
-                                          Frag (*bl)[ZKS][64], int pb, int ch, int pc0, int qg,
-                                          int p1, int L) {
+__device__ __forceinline__ void put_chunk(const ChunkRegs<ST, NI>& r, const BlockItems<NI>& it,
+                                          Frag (*bh)[ZKS][64], Frag (*bl)[ZKS][64], int pb,
+                                          int ch, int pc0, int qg, int p1, int L) {
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const int pc = pc0 + 16 * i;
@@ -217,8 +235,8 @@ __device__ __forceinline__ void put_chunk(const ChunkRegs<ST, NI>& r, Frag (*bh)
       const float2 c = keep ? r.c[i][s2] : make_float2(0.f, 0.f);
       const float2 w = r.w[s2];
       const float2 d = make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
-      const float2 y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * r.scale[i],
-                                   fmaf(d.x, w.y, d.y * w.x) * r.scale[i]);
+      const float2 y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * it.scale[i],
+                                   fmaf(d.x, w.y, d.y * w.x) * it.scale[i]);
       uint32_t rh, rl, ih, il;
       split2<PREC>(y.x, rh, rl);
       split2<PREC>(y.y, ih, il);
@@ -298,10 +316,14 @@ __global__ void __launch_bounds__(ZTA) zoom_spectra(ZoomArgs a) {
     auto build = [&](auto vec) {
       constexpr bool VEC = decltype(vec)::value;
       ChunkRegs<ST, NI> r;
+      BlockItems<NI> it;
       for (int pb = p0; pb < p1; pb += NCOL) {
+        block_items<PREC, NI>(a, it, pb, pc0, p0, p1, gate_off);
         for (int ch = 0; ch < nchunks; ++ch) {
-          fetch_chunk<PREC, ST, NI, VEC>(a, r, pb, ch, pc0, qg, p0, p1, gate_off, k0);
-          put_chunk<PREC, ST, NI>(r, bh[ch & 1], bl[ch & 1], pb, ch, pc0, qg, p1, L);
+          fetch_chunk<ST, NI, VEC>(a, r, it, ch, qg, k0);
+          // every load of the chunk is issued before the first use of any
+          __builtin_amdgcn_sched_barrier(0);
+          put_chunk<PREC, ST, NI>(r, it, bh[ch & 1], bl[ch & 1], pb, ch, pc0, qg, p1, L);
           __syncthreads();
         }
         __syncthreads();  // the block's last chunk is consumed
