@@ -601,18 +601,238 @@ __global__ void __launch_bounds__(FW_THREADS) net_forward_bf16(const float* __re
   for (int m = 0; m < FW_PER_THREAD; ++m) out[j + FW_THREADS * m] = acc[m];
 }
 
+// Forward split over S workgroups per gate, for batches too small to fill the
+// chip with one workgroup per gate.  Part q owns the W = T / S output
+// positions [a, a + W), a = q W, and computes layers 1..3 on the 32-aligned
+// range [a - 32, a + W + 32) (W / 32 + 2 tiles, two per wave), enough for the
+// 3-position halo that each later 7-tap layer consumes; the edge tiles read
+// zero margin rows and are not used.  Every output takes the same operations
+// in the same order as in net_forward_bf16 (the input stage reproduces its
+// reduction tree over the whole row), so the logits are bit-identical.
+template <int S>
+struct SplitGeo {
+  static constexpr int W = T / S;            // output positions per part
+  static constexpr int NL = W + 64;          // computed positions per layer
+  static constexpr int WAVES = NL / 64;      // matrix-layer waves: two 32-position tiles each
+  // at least one wave per input-stage wave, so the row sum takes one pass
+  static constexpr int THREADS = 64 * (WAVES > FW_IN_WAVES ? WAVES : FW_IN_WAVES);
+  static constexpr int ROWS = NL + 2 * PAD;  // local rows: PAD zero margins each side
+  static_assert(W % 64 == 0 && THREADS >= W, "split tiling");
+};
+
+// One 32-channel layer over the local rows (row u + PAD holds position
+// a - 32 + u); same per-output arithmetic as mfma_layer.
+template <int S>
+__device__ __forceinline__ void mfma_layer_split(const uint16_t* __restrict__ src,
+                                                 uint16_t* __restrict__ dst,
+                                                 const Frag8 (*__restrict__ wt)[64],
+                                                 const float* bias, int wave, int lane) {
+  const int h = lane >> 5, c = lane & 31;
+  Frag8 afr[14];
+#pragma unroll
+  for (int ks = 0; ks < 14; ++ks) afr[ks] = wt[ks][lane];
+  float bv[16];
+  load_bias(bias, h, bv);
+  // all weight loads in flight before the first multiply (left to itself the
+  // scheduler spreads them between the multiplies, one latency each)
+  __builtin_amdgcn_sched_barrier(0);
+  auto bfrag = [&](int u, int ks) {
+    const int kk = ks >> 1, ci0 = 16 * (ks & 1) + 8 * h;
+    return *reinterpret_cast<const Frag8*>(src + act_idx(u + kk, ci0));  // row (u + PAD) + kk - PAD
+  };
+  const int u0 = 64 * wave + c, u1 = u0 + 32;
+  nf32x16 acc0, acc1;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    acc0[r] = 0.f;
+    acc1[r] = 0.f;
+  }
+  Frag8 b0 = bfrag(u0, 0), b1 = bfrag(u1, 0);
+#pragma unroll
+  for (int ks = 0; ks < 14; ++ks) {
+    Frag8 n0 = b0, n1 = b1;
+    if (ks + 1 < 14) {
+      n0 = bfrag(u0, ks + 1);
+      n1 = bfrag(u1, ks + 1);
+    }
+    acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, afr[ks]),
+                                                   __builtin_bit_cast(nbf16x8, b0), acc0, 0, 0, 0);
+    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, afr[ks]),
+                                                   __builtin_bit_cast(nbf16x8, b1), acc1, 0, 0, 0);
+    b0 = n0;
+    b1 = n1;
+  }
+  store_tile(acc0, bv, h, u0 + PAD, dst);
+  store_tile(acc1, bv, h, u1 + PAD, dst);
+}
+
+template <bool FROM_SPECTRA, int S>
+__global__ void __launch_bounds__(SplitGeo<S>::THREADS)
+net_forward_split(const float* __restrict__ x, const NetBf16* __restrict__ nw,
+                  float* __restrict__ logits, const float* __restrict__ partial, int32_t chunks,
+                  float* __restrict__ x_out, int32_t batch) {
+  using Geo = SplitGeo<S>;
+  constexpr int W = Geo::W, NL = Geo::NL, ROWS = Geo::ROWS;
+  __shared__ __attribute__((aligned(16))) float row_s[T];  // the gate's whole input row
+  __shared__ __attribute__((aligned(16))) float xs[ROWS];  // local features
+  __shared__ __attribute__((aligned(16))) uint16_t act0[ROWS * 32];
+  __shared__ __attribute__((aligned(16))) uint16_t act1[ROWS * 32];
+  __shared__ float red[FW_IN_WAVES];
+  __shared__ float w4s[32 * TAPS];
+  const int b = blockIdx.x, q = b / batch, g = b - q * batch;
+  const int a = q * W;
+  const int j = threadIdx.x, lane = j & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(j >> 6);
+  const int h = lane >> 5, c = lane & 31;
+  if (j < 32 * TAPS) w4s[j] = nw->w4[j];
+  // zero margin rows of both activation buffers
+  for (int e = j; e < 2 * PAD * 32; e += Geo::THREADS) {
+    const int r = e / 32 < PAD ? e / 32 : NL + e / 32;  // rows 0..PAD-1 and NL+PAD..NL+2PAD-1
+    act0[r * 32 + e % 32] = 0;
+    act1[r * 32 + e % 32] = 0;
+  }
+  // input stage over the whole row: thread j < FW_IN_THREADS holds positions
+  // 2 j, 2 j + 1 and wave w its share of the total, exactly as the
+  // one-workgroup forward does, so the row total is the same float
+  if (wave < FW_IN_WAVES) {
+    const int jj = j;
+    const int vw = wave;
+    float2 v;
+    if (FROM_SPECTRA && chunks > 1) {
+      const int64_t cs = static_cast<int64_t>(batch) * T;
+      const float2* pr =
+          reinterpret_cast<const float2*>(partial + static_cast<int64_t>(g) * T) + jj;
+      v = make_float2(0.f, 0.f);
+      // sixteen loads in flight, then the sums in ascending chunk order
+      for (int c0 = 0; c0 < chunks; c0 += 16) {
+        float2 qv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          qv[u] = c0 + u < chunks ? pr[(c0 + u) * (cs / 2)] : make_float2(0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (c0 + u < chunks) {
+            v.x += qv[u].x;
+            v.y += qv[u].y;
+          }
+      }
+    } else {
+      v = reinterpret_cast<const float2*>(x + static_cast<int64_t>(g) * T)[jj];
+    }
+    reinterpret_cast<float2*>(row_s)[jj] = v;
+    if (FROM_SPECTRA) {
+      float sum = v.x + v.y;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+      if (lane == 0) red[vw] = sum;
+    }
+  }
+  __syncthreads();
+  float inv = 1.f;
+  if (FROM_SPECTRA) {
+    float tot = 0.f;
+#pragma unroll
+    for (int w = 0; w < FW_IN_WAVES; ++w) tot += red[w];  // fixed order
+    inv = 1.f / (tot / static_cast<float>(T));
+    if (chunks > 1 && j < W) x_out[static_cast<int64_t>(g) * T + a + j] = row_s[a + j];
+  }
+  // features of the local rows: row u + PAD holds position a - 32 + u (mod T)
+  for (int u = j - PAD; u < NL + PAD; u += Geo::THREADS) {
+    const float sv = row_s[(a - 32 + u) & (T - 1)];
+    xs[u + PAD] = FROM_SPECTRA ? logf(fmaxf(sv * inv, 1e-30f)) : sv;
+  }
+  __syncthreads();
+  // layer 1: one k-step, B[k][u] = bf16(x[u + k - 3]) for k < 7
+  const bool mat = wave < Geo::WAVES;  // whole waves
+  if (mat) {
+    const Frag8 a1 = nw->w1[lane];
+    float bv[16];
+    load_bias(nw->b1, h, bv);
+#pragma unroll
+    for (int tile = 0; tile < 2; ++tile) {
+      const int u = 64 * wave + 32 * tile + c;
+      Frag8 bfr;
+#pragma unroll
+      for (int i = 0; i < 8; i += 2) {
+        uint32_t lo = 0, hi = 0;
+        if (h == 0) {
+          lo = to_bf16(xs[u + i]);  // local row u + PAD + i - PAD
+          if (i + 1 < TAPS) hi = to_bf16(xs[u + i + 1]);
+        }
+        bfr.w[i / 2] = lo | (hi << 16);
+      }
+      nf32x16 acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(nbf16x8, a1),
+                                                    __builtin_bit_cast(nbf16x8, bfr), acc, 0, 0, 0);
+      store_tile(acc, bv, h, u + PAD, act0);
+    }
+  }
+  __syncthreads();
+  if (mat) mfma_layer_split<S>(act0, act1, nw->w2, nw->b2, wave, lane);
+  __syncthreads();
+  if (mat) mfma_layer_split<S>(act1, act0, nw->w3, nw->b3, wave, lane);
+  __syncthreads();
+  // layer 4 on the part's W positions: thread j < W takes position a + j
+  // (local u = 32 + j), in the one-workgroup forward's order
+  if (j < W) {
+    const int u = 32 + j;
+    float acc = nw->b4;
+#pragma unroll 1
+    for (int qq = 0; qq < 4; ++qq) {
+#pragma unroll
+      for (int kk = 0; kk < TAPS; ++kk) {
+        float w[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) w[i] = w4s[(8 * qq + i) * TAPS + kk];
+        const uint4 u4 = *reinterpret_cast<const uint4*>(act0 + act_idx(u + kk, 8 * qq));
+        const uint32_t uu[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          acc = fmaf(w[2 * i], __uint_as_float(uu[i] << 16), acc);
+          acc = fmaf(w[2 * i + 1], __uint_as_float(uu[i] & 0xffff0000u), acc);
+        }
+      }
+    }
+    logits[static_cast<int64_t>(g) * T + a + j] = acc;
+  }
+}
+
 }  // namespace
 
 size_t net_bf16_bytes() { return sizeof(NetBf16); }
+
+constexpr int kSplitFourMax = 128;  // batches up to this many gates: four parts per gate
+constexpr int kSplitTwoMax = 256;   // up to this many: two parts
 
 hipError_t launch_net_prep_bf16(const float* params, void* table, hipStream_t s) {
   hipLaunchKernelGGL(prep_bf16, dim3(1), dim3(256), 0, s, params, static_cast<NetBf16*>(table));
   return hipGetLastError();
 }
 
+template <int S>
+hipError_t launch_split(const void* table, const float* x, int batch, float* logits, hipStream_t s,
+                        bool from_spectra, const float* partial, int32_t chunks, float* x_out) {
+  const dim3 grid(static_cast<unsigned>(batch) * S), block(SplitGeo<S>::THREADS);
+  const NetBf16* nw = static_cast<const NetBf16*>(table);
+  if (from_spectra)
+    hipLaunchKernelGGL((net_forward_split<true, S>), grid, block, 0, s, x, nw, logits, partial,
+                       chunks, x_out, batch);
+  else
+    hipLaunchKernelGGL((net_forward_split<false, S>), grid, block, 0, s, x, nw, logits, nullptr, 1,
+                       nullptr, batch);
+  return hipGetLastError();
+}
+
 hipError_t launch_net_forward_bf16(const void* table, const float* x, int batch, float* logits,
                                    hipStream_t s, bool from_spectra, const float* partial,
                                    int32_t chunks, float* x_out) {
+  // fewer gates than compute units: several workgroups per gate
+  if (batch <= kSplitFourMax)
+    return launch_split<4>(table, x, batch, logits, s, from_spectra, partial, chunks, x_out);
+  if (batch <= kSplitTwoMax)
+    return launch_split<2>(table, x, batch, logits, s, from_spectra, partial, chunks, x_out);
   if (from_spectra)
     hipLaunchKernelGGL(net_forward_bf16<true>, dim3(batch), dim3(FW_THREADS), 0, s, x,
                        static_cast<const NetBf16*>(table), logits, partial, chunks, x_out);

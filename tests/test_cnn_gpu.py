@@ -124,3 +124,24 @@ def test_forward_bf16_matrix_cores_within_bf16_bound(ispl):
     # an empty batch is a no-op
     net.forward(xs[:0], precision="bf16")
     net.close()
+
+
+def test_forward_bf16_split_workgroups_bit_identical(ispl):
+    """Batches up to 128 gates run each gate on four workgroups, up to 256 on
+    two (each part recomputes a 12-position halo), larger ones on one.  Every
+    logit must be bit-identical whichever tiling computed it; rows 0, 63 and
+    the last rows also against the FP64 oracle within the BF16 bound."""
+    p, X, _ = batch(11, 300)
+    X[5] *= 8.0
+    X[77] = np.roll(X[77], 511)
+    net = ispl.Net(1)
+    net.set_params(p)
+    xs = torch.from_numpy(X).to(DEV)
+    whole = net.forward(xs, precision="bf16").cpu().numpy()  # 300 gates: one workgroup each
+    for B in (1, 64, 128, 129, 200, 256):
+        part = net.forward(xs[:B].contiguous(), precision="bf16").cpu().numpy()
+        assert np.array_equal(part.view(np.uint32), whole[:B].view(np.uint32)), B
+    for b in (0, 63, 299):
+        ref, _ = cnn.forward(p, X[b].astype(np.float64))
+        assert np.max(np.abs(whole[b] - ref)) <= 2e-2 * np.abs(ref).max(), b
+    net.close()
