@@ -33,15 +33,32 @@ __device__ __forceinline__ void pulse_exponent_block(const void* __restrict__ sa
   __shared__ float red[2][4];
   float mx = 0.f, mc = 0.f;
   const int64_t base = static_cast<int64_t>(p) * stride;
-  for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
-    const float2 x = load_any_sample(samples, sample_type, base + i);
-    mx = fmaxf(mx, x.x * x.x + x.y * x.y);
+  // eight loads in flight per thread (indices clamped into the span, the
+  // clamped ones counted as zero); the maximum does not depend on the order
+  constexpr int U = 8;
+  for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += 256 * U) {
+    float2 x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + 256 * u;
+      x[u] = load_any_sample(samples, sample_type, base + (i < hi ? i : hi - 1));
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (i0 + 256 * u < hi) mx = fmaxf(mx, x[u].x * x[u].x + x[u].y * x[u].y);
   }
   const float2* txp = reinterpret_cast<const float2*>(tx) +
                       (tx_per_pulse ? static_cast<int64_t>(p) * code_len : 0);
-  for (int n = threadIdx.x; n < code_len; n += 256) {
-    const float2 c = txp[n];
-    mc = fmaxf(mc, c.x * c.x + c.y * c.y);
+  for (int n0 = threadIdx.x; n0 < code_len; n0 += 256 * U) {
+    float2 c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int n = n0 + 256 * u;
+      c[u] = txp[n < code_len ? n : code_len - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (n0 + 256 * u < code_len) mc = fmaxf(mc, c[u].x * c[u].x + c[u].y * c[u].y);
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
