@@ -228,11 +228,11 @@ __device__ __forceinline__ void put_chunk(const ChunkRegs<ST, NI>& r, const Bloc
     Frag fh, fl;
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
-      // samples past L and pulses past the range contribute zero
+      // samples past L and pulses past the range contribute zero (their
+      // split words are cleared; they were fetched from valid addresses)
       const bool keep = live && ch * ZCHUNK + 4 * qg + s2 < L;
-      const float2 xr = to_complex(r.x[i][s2]);
-      const float2 x = keep ? xr : make_float2(0.f, 0.f);
-      const float2 c = keep ? r.c[i][s2] : make_float2(0.f, 0.f);
+      const float2 x = to_complex(r.x[i][s2]);
+      const float2 c = r.c[i][s2];
       const float2 w = r.w[s2];
       const float2 d = make_float2(fmaf(c.x, x.x, c.y * x.y), fmaf(c.x, x.y, -(c.y * x.x)));
       const float2 y = make_float2(fmaf(d.x, w.x, -(d.y * w.y)) * it.scale[i],
@@ -240,8 +240,8 @@ __device__ __forceinline__ void put_chunk(const ChunkRegs<ST, NI>& r, const Bloc
       uint32_t rh, rl, ih, il;
       split2<PREC>(y.x, rh, rl);
       split2<PREC>(y.y, ih, il);
-      fh.w[s2] = rh | (ih << 16);
-      fl.w[s2] = rl | (il << 16);
+      fh.w[s2] = keep ? rh | (ih << 16) : 0u;
+      fl.w[s2] = keep ? rl | (il << 16) : 0u;
     }
     const int ks = qg >> 1, ln = (pc & 31) + 32 * (qg & 1), ct = pc >> 5;
     bh[ct][ks][b_slot(ks, ln)] = fh;
