@@ -201,6 +201,32 @@ __device__ __forceinline__ void row_transpose4(float (&m)[4]) {
 template <int ST>
 struct SampleIO;
 
+// The same global-memory pointer, read from the first active lane: for
+// values that are uniform over the workgroup, so that they stay in scalar
+// registers and loads through them take a scalar base and a 32-bit lane offset.
+// Element types are read as builtin types (complex64 as a 2-vector), since
+// the class types cannot be loaded through an address-space pointer.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <typename T>
+struct Builtin {
+  using type = T;
+};
+template <>
+struct Builtin<float2> {
+  using type = f32x2;
+};
+template <typename T>
+using gptr = const __attribute__((address_space(1))) typename Builtin<T>::type*;
+template <typename T>
+__device__ __forceinline__ gptr<T> uniform_ptr(const T* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+  return reinterpret_cast<gptr<T>>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+__device__ __forceinline__ uint32_t from_builtin(uint32_t v) { return v; }
+__device__ __forceinline__ float2 from_builtin(f32x2 v) { return make_float2(v.x, v.y); }
+
 template <>
 struct SampleIO<0> {  // complex64
   using raw_t = float2;
@@ -379,14 +405,19 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   raw_t raw[E];
   float2 cod[E];
   auto load = [&](int p) {
-    const int64_t rowp = static_cast<int64_t>(p) * a.stride + gate_off;
-    const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0);
+    // per-pulse row bases as workgroup-uniform values: the loads then take a
+    // scalar base plus a 32-bit lane offset, and no per-lane 64-bit pointer
+    // is kept live across the pulse loop
+    const gptr<raw_t> srow = uniform_ptr(reinterpret_cast<const raw_t*>(a.samples) +
+                                         (static_cast<int64_t>(p) * a.stride + gate_off));
+    const gptr<float2> txp =
+        uniform_ptr(txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0));
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int n = tid + i * NT;
       if (n < L) {
-        raw[i] = IO::load(a.samples, rowp + n);
-        cod[i] = txp[n];
+        raw[i] = from_builtin(srow[static_cast<uint32_t>(n)]);
+        cod[i] = from_builtin(txp[static_cast<uint32_t>(n)]);
       } else {
         raw[i] = IO::zero();
         cod[i] = make_float2(0.f, 0.f);
