@@ -558,14 +558,16 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
   raw_t nr[2] = {IO::zero(), IO::zero()};
   float2 nc[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
   auto fetch2 = [&](int p) {
-    const int64_t rowp = static_cast<int64_t>(p) * a.stride + gate_off;
-    const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0);
+    const gptr<raw_t> srow = uniform_ptr(reinterpret_cast<const raw_t*>(a.samples) +
+                                         (static_cast<int64_t>(p) * a.stride + gate_off));
+    const gptr<float2> txp =
+        uniform_ptr(txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0));
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int n = tid + 1024 * j;
       if (n < L) {
-        nr[j] = IO::load(a.samples, rowp + n);
-        nc[j] = txp[n];
+        nr[j] = from_builtin(srow[static_cast<uint32_t>(n)]);
+        nc[j] = from_builtin(txp[static_cast<uint32_t>(n)]);
       } else {
         nr[j] = IO::zero();
         nc[j] = make_float2(0.f, 0.f);
@@ -582,13 +584,16 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
       if (p + 1 < p1) fetch2(p + 1);
       two_point_pass<ST>(v, y0, cmul(y1, xpre[1]), dk);
     } else {
-      const int64_t rowp = static_cast<int64_t>(p) * a.stride + gate_off;
-      const float2* txp = txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0);
+      const gptr<raw_t> srow = uniform_ptr(reinterpret_cast<const raw_t*>(a.samples) +
+                                           (static_cast<int64_t>(p) * a.stride + gate_off));
+      const gptr<float2> txp =
+          uniform_ptr(txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0));
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const int n = tid + 1024 * j;
-        v[j] = n < L ? conj_mul(txp[n], IO::cvt(IO::load(a.samples, rowp + n)))
-                     : make_float2(0.f, 0.f);
+        const uint32_t n = static_cast<uint32_t>(tid + 1024 * j);
+        v[j] = n < static_cast<uint32_t>(L)
+                   ? conj_mul(from_builtin(txp[n]), IO::cvt(from_builtin(srow[n])))
+                   : make_float2(0.f, 0.f);
       }
       dft16_pre1(v, xpre, dk);
     }
