@@ -356,7 +356,10 @@ __global__ void __launch_bounds__(ZTA) zoom_spectra(ZoomArgs a) {
   // A fragments are fetched AD k-steps ahead into a ring (slot ks % AD, which
   // AD | ZKS makes static).  The refill after the last k-step of a pulse
   // block wraps to the first ones, which the next block uses.
-  constexpr int AD = 2;
+  // Four k-steps ahead where the registers allow it (one column tile): on
+  // small launches every workgroup reaches the same k-steps at once, so the
+  // table misses are not warmed in L2 by anyone ahead.
+  constexpr int AD = CT == 1 ? 4 : 2;
   static_assert(ZKS % AD == 0, "static ring slots");
   Frag ah[AD][RT], al[AD][RT];
 #pragma unroll
