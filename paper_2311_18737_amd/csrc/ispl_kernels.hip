@@ -165,6 +165,14 @@ __device__ __forceinline__ void dft16(float2 (&v)[16], const Dft16Consts& k) {
   dft16_stage_b(v, k);
 }
 
+// 16-point DFT of v when v[4..15] are zero: the first radix-4 stage then
+// only replicates v[j1] (the 4-point DFT of (a, 0, 0, 0) is (a, a, a, a)).
+__device__ __forceinline__ void dft16_first4(float2 (&v)[16], const Dft16Consts& k) {
+#pragma unroll
+  for (int j1 = 0; j1 < 4; ++j1) v[j1 + 4] = v[j1 + 8] = v[j1 + 12] = v[j1];
+  dft16_stage_b(v, k);
+}
+
 // 16-point forward DFT of (w[j] v[j]).
 __device__ __forceinline__ void dft16_pre(float2 (&v)[16], const float2 (&w)[16],
                                           const Dft16Consts& k) {
@@ -280,14 +288,18 @@ __device__ __forceinline__ void load_wave_twiddles(WaveTwiddles& w, const float2
 // acc[4 t + kd] += |F[kb]|^2 for kb = ka + 16 (4 row + t) + 256 kd, with
 // ka = lane & 15, row = lane >> 4 (F including the bin-class factors).
 // K0: the wave's bin class is 0 (N = 1024), so the pass-1 factors are all 1.
-template <bool K0 = false>
+// F4 (with K0): only v[0..3] carry samples (L <= 256); v[4..15] are not read.
+template <bool K0 = false, bool F4 = false>
 __device__ __forceinline__ void wave_fft_accumulate(float2 (&v)[16], float2* xw,
                                                     const WaveTwiddles& w,
                                                     const Dft16Consts& dk, float (&acc)[16],
                                                     int lane) {
   const int ka = lane & 15, row = lane >> 4;
   // pass 1: pre-twiddle and 16-point DFT over the stride-64 samples of a lane
-  if constexpr (K0)
+  static_assert(!F4 || K0, "four non-zero inputs only in bin class 0");
+  if constexpr (F4)
+    dft16_first4(v, dk);
+  else if constexpr (K0)
     dft16(v, dk);
   else
     dft16_pre1(v, w.pre, dk);
@@ -360,12 +372,15 @@ __device__ __forceinline__ float* out_row(const FusedArgs& a, int g, int c) {
 // transform, for launches too small to hide memory latency with other waves
 // (the extra registers cost a wave per SIMD on large launches).  K0 (one-wave
 // workgroups at N = 1024 only): the single bin class is 0, so pass 1 has no
-// pre-twiddles.
-template <int RW, int ST, bool PF = false, bool K0 = false>
+// pre-twiddles.  F4 (with K0, L <= 256): each lane's samples 4..15 are zero,
+// so they are neither fetched nor decoded and pass 1 starts from four inputs.
+template <int RW, int ST, bool PF = false, bool K0 = false, bool F4 = false>
 __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   static_assert(!K0 || RW == 1, "bin class 0 alone: one-wave workgroups at N = 1024");
+  static_assert(!F4 || K0, "four non-zero inputs only in bin class 0");
   constexpr int NT = 64 * RW;
   constexpr int E = SUB / NT;          // decoded samples staged per thread
+  constexpr int EL = F4 ? 4 : E;       // of which can be non-zero
   constexpr bool DBUF = (RW == 16);    // double-buffer the decoded row when LDS allows
   using IO = SampleIO<ST>;
   using raw_t = typename IO::raw_t;
@@ -413,7 +428,7 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
     const gptr<float2> txp =
         uniform_ptr(txb + (a.tx_per_pulse ? static_cast<int64_t>(p) * L : 0));
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
+    for (int i = 0; i < EL; ++i) {
       const int n = tid + i * NT;
       if (n < L) {
         raw[i] = from_builtin(srow[static_cast<uint32_t>(n)]);
@@ -436,9 +451,9 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
       for (int p = p0; p < p1; ++p) {
         float2 v[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
+        for (int j = 0; j < EL; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
         if (p + 1 < p1) load(p + 1);
-        wave_fft_accumulate<K0>(v, xw, wt, dk, acc, lane);
+        wave_fft_accumulate<K0, F4>(v, xw, wt, dk, acc, lane);
       }
     } else {
       // the other waves on the SIMD hide the load latency
@@ -446,8 +461,8 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
         load(p);
         float2 v[16];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
-        wave_fft_accumulate<K0>(v, xw, wt, dk, acc, lane);
+        for (int j = 0; j < EL; ++j) v[j] = conj_mul(cod[j], IO::cvt(raw[j]));
+        wave_fft_accumulate<K0, F4>(v, xw, wt, dk, acc, lane);
       }
     }
   } else {
@@ -750,8 +765,13 @@ hipError_t launch_fused_t(const FusedArgs& a, hipStream_t stream) {
   constexpr int64_t kPrefetchMaxWaves = 2 * 4 * 256;
   if constexpr (RW == 1) {
     const bool pf = blocks <= kPrefetchMaxWaves, k0 = a.log2_r == 0;
+    const bool f4 = k0 && a.code_len <= 4 * 64;  // lane samples 4..15 all past L
     const dim3 grid(static_cast<unsigned>(blocks)), block(64);
-    if (pf && k0)
+    if (pf && f4)
+      hipLaunchKernelGGL((fused_spectra<1, ST, true, true, true>), grid, block, 0, stream, a);
+    else if (f4)
+      hipLaunchKernelGGL((fused_spectra<1, ST, false, true, true>), grid, block, 0, stream, a);
+    else if (pf && k0)
       hipLaunchKernelGGL((fused_spectra<1, ST, true, true>), grid, block, 0, stream, a);
     else if (pf)
       hipLaunchKernelGGL((fused_spectra<1, ST, true, false>), grid, block, 0, stream, a);

@@ -64,6 +64,9 @@ SHAPES = [
     (1024, 256, 17, 33, 25, 0, "c64", True, "gauss"),
     # one-wave workgroups on a launch of more than two waves per SIMD (no prefetch)
     (1024, 256, 300, 80, 5, 0, "ci16", True, "bpsk"),
+    # either side of the four-input first pass at N = 1024 (L <= 256)
+    (1024, 257, 9, 6, 25, 1, "c64", True, "gauss"),
+    (1024, 200, 3, 4, 25, 2, "ci16", False, "bpsk"),
     (2048, 65, 5, 7, 25, 11, "c64", True, "phase"),
     (4096, 1000, 4, 9, 25, 0, "ci16", True, "bpsk"),
     (8192, 333, 3, 4, 10, 5, "c64", False, "phase"),
