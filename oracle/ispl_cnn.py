@@ -4,9 +4,9 @@ TEST INFRASTRUCTURE ONLY (tests and benchmark); the GPU kernels share no code
 with it.
 
 The network reads one integrated coarse spectrum per gate, as the feature
-x[t] = log(S[t] / mean_t S), and returns one logit per coarse bin.  Four
-circular 1-D convolutions with 7 taps: 1 -> 32 -> 32 -> 32 -> 1 channels,
-ReLU after the first three.  A gate's target is the position u of its
+x[t] = log(max(S[t] / mean_t S, 1e-30)), and returns one logit per coarse
+bin.  Four circular 1-D convolutions with 7 taps: 1 -> 32 -> 32 -> 32 -> 1
+channels, ReLU after the first three.  A gate's target is the position u of its
 plasma line in coarse-bin units (a real number, from the full-resolution
 spectrum); the loss is the cross entropy of the softmax over bins against
 the two-hot distribution that puts 1 - frac(u) on floor(u) and frac(u) on
@@ -53,10 +53,21 @@ def unpack(params: np.ndarray):
     return out
 
 
+FEATURE_FLOOR = 1e-30
+
+
 def features(spectra: np.ndarray) -> np.ndarray:
-    """log(S / mean S) per row."""
+    """x[t] = log(max(S[t] / mean S, 1e-30)) per row.
+
+    The floor keeps bins that hold no power finite (log 1e-30 = -69.08); an
+    all-zero row has no defined ratio and is taken as ratio 0, i.e. the
+    floor in every bin.
+    """
     s = np.asarray(spectra, dtype=np.float64)
-    return np.log(s / s.mean(axis=-1, keepdims=True))
+    mean = s.mean(axis=-1, keepdims=True)
+    safe = np.where(mean > 0, mean, 1.0)
+    ratio = np.where(mean > 0, s / safe, 0.0)
+    return np.log(np.maximum(ratio, FEATURE_FLOOR))
 
 
 def conv_circ(a: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:

@@ -1,8 +1,8 @@
 // Window-proposal network of the learned zoom: training kernels (FP32 on
 // the vector ALUs).
 //
-// The network maps one gate's coarse spectrum feature x[t] = log(S[t] / mean S),
-// t < T = 1024, to one logit per coarse bin through four circular 7-tap 1-D
+// The network maps one gate's coarse spectrum feature
+// x[t] = log(max(S[t] / mean S, 1e-30)), t < T = 1024, to one logit per coarse bin through four circular 7-tap 1-D
 // convolutions, 1 -> 32 -> 32 -> 32 -> 1 channels with ReLU after the first
 // three.  Training minimises the softmax cross entropy against a two-hot
 // target at the line's coarse position u (1 - frac(u) on floor(u), frac(u)

@@ -95,6 +95,15 @@ def test_features_match_oracle(ispl):
     got = net.features(torch.from_numpy(S).to(DEV)).cpu().numpy()
     ref = cnn.features(S.astype(np.float64))
     assert np.max(np.abs(got - ref)) <= 2e-6 * np.abs(ref).max() + 1e-6
+    # bins without power take the floor log(1e-30), and an all-zero row is
+    # the floor everywhere (float32 log of 1e-30: within a few units of its
+    # last place, about 8e-6 at -69)
+    Z = np.zeros((2, 1024), dtype=np.float32)
+    Z[0, ::7] = rng.exponential(1.0, Z[0, ::7].shape) * 1e3
+    got = net.features(torch.from_numpy(Z).to(DEV)).cpu().numpy()
+    ref = cnn.features(Z.astype(np.float64))
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got - ref)) <= 3e-5, np.max(np.abs(got - ref))
     net.close()
 
 

@@ -121,3 +121,121 @@ def test_batch_gradient_is_mean():
     parts = [cnn.loss_and_grad(p, X[i], U[i]) for i in range(3)]
     assert abs(l - np.mean([q[0] for q in parts])) < 1e-12
     np.testing.assert_allclose(g, np.mean([q[1] for q in parts], axis=0), rtol=1e-12, atol=1e-15)
+
+
+# ------------------------------------------------------------- features
+def test_features_hand_worked():
+    """S = (1, 3): mean 2, x = (log 1/2, log 3/2)."""
+    x = cnn.features(np.array([[1.0, 3.0]]))
+    np.testing.assert_allclose(x, [[np.log(0.5), np.log(1.5)]], rtol=0, atol=1e-15)
+
+
+def test_features_scale_invariant_and_normalised():
+    """log(S / mean S) does not change when S is scaled, and exp(x) has mean 1
+    (every bin above the floor).  Catches a missing or wrong normalisation
+    (sum, max or median instead of the mean; a log without the division)."""
+    rng = np.random.default_rng(8)
+    S = rng.exponential(1.0, (4, 1024)) * 10.0 ** rng.uniform(-3, 6, (4, 1))
+    x = cnn.features(S)
+    for c in (1e-12, 0.37, 3.0, 1e9):
+        np.testing.assert_allclose(cnn.features(c * S), x, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(np.exp(x).mean(axis=1), 1.0, rtol=0, atol=1e-12)
+    # a constant row is at its mean everywhere
+    np.testing.assert_array_equal(cnn.features(np.full((2, 64), 5.5)), 0.0)
+
+
+def test_features_floor_on_zero_bins():
+    """Bins without power sit at log(1e-30); the others at log(S T / sum S).
+    An all-zero row is the floor in every bin.  Catches a missing floor
+    (-inf), a floor applied to S instead of the ratio, and a floor value
+    other than 1e-30."""
+    T = 16
+    S = np.zeros((3, T))
+    S[0, 3], S[0, 9] = 2.0, 6.0          # two bins with power
+    S[1] = 1e-40                         # tiny but positive: ratio 1, not the floor
+    x = cnn.features(S)
+    floor = np.log(1e-30)
+    assert np.all(np.isfinite(x))
+    want0 = np.full(T, floor)
+    want0[3], want0[9] = np.log(2.0 * T / 8.0), np.log(6.0 * T / 8.0)
+    np.testing.assert_allclose(x[0], want0, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(x[1], 0.0, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(x[2], floor, rtol=0, atol=1e-12)
+    # a ratio just above the floor is kept as is
+    S2 = np.full((1, 4), 1.0)
+    S2[0, 0] = 1e-29
+    r0 = 1e-29 / S2.mean()
+    assert r0 > 1e-30
+    np.testing.assert_allclose(cnn.features(S2)[0, 0], np.log(r0), rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------- closed-form forward
+def hand_set_params():
+    """Weights whose logits follow in closed form (r = ReLU).  Every used tap
+    is a delta; channel c of layers 2 and 3 reads only channel c:
+      channel 0: a3 = r(r(r(x)))                      layer-1 weight 1
+      channel 1: a3 = r(r(r(-x)) - 1/2)               weight -1, layer-3 bias -1/2
+      channel 2: a3 = r(r(r(x) - 1) + 1/4)            layer-2 bias -1, layer-3 bias 1/4
+      channel 3: a3 = r(r(r(x - 1) + 1/2))            layer-1 bias -1, layer-2 bias 1/2
+      logits[t] = -3 + a3_0[t] + 2 a3_1[t] + 4 a3_2[t] + 2 a3_3[t] + a3_0[(t + 2) mod T]
+    (layer 4: centre taps 1, 2, 4, 2 and channel 0's tap k = 5 with weight 1,
+    bias -3).  A positive bias after a layer whose pre-activation is negative
+    exposes that layer's ReLU (channels 2 and 3), a negative one the ReLU and
+    the bias placement of the layer it belongs to (channel 1)."""
+    flat = np.zeros(cnn.N_PARAMS)
+    off = []  # (first weight, first bias) of each layer in the flat vector
+    o = 0
+    for cin, cout, _ in cnn.LAYERS:
+        off.append((o, o + cout * cin * cnn.TAPS))
+        o += cout * cin * cnn.TAPS + cout
+
+    def W(li, co, ci, k, v):
+        w0, _ = off[li]
+        cin = cnn.LAYERS[li][0]
+        flat[w0 + (co * cin + ci) * cnn.TAPS + k] = v
+
+    def b(li, co, v):
+        _, b0 = off[li]
+        flat[b0 + co] = v
+
+    c = cnn.PAD
+    W(0, 0, 0, c, 1.0)
+    W(0, 1, 0, c, -1.0)
+    W(0, 2, 0, c, 1.0)
+    W(0, 3, 0, c, 1.0)
+    b(0, 3, -1.0)
+    for ch in range(4):
+        W(1, ch, ch, c, 1.0)
+        W(2, ch, ch, c, 1.0)
+    b(1, 2, -1.0)
+    b(1, 3, 0.5)
+    b(2, 1, -0.5)
+    b(2, 2, 0.25)
+    W(3, 0, 0, c, 1.0)
+    W(3, 0, 1, c, 2.0)
+    W(3, 0, 2, c, 4.0)
+    W(3, 0, 3, c, 2.0)
+    W(3, 0, 0, c + 2, 1.0)
+    b(3, 0, -3.0)
+    return flat
+
+
+def closed_form_logits(x):
+    r = lambda v: np.maximum(v, 0.0)  # noqa: E731
+    a0 = r(x)
+    a1 = r(r(-x) - 0.5)
+    a2 = r(r(r(x) - 1.0) + 0.25)
+    a3 = r(x - 1.0) + 0.5
+    return -3.0 + a0 + 2.0 * a1 + 4.0 * a2 + 2.0 * a3 + np.roll(a0, -2)
+
+
+def test_forward_closed_form_hand_set_weights():
+    """Logits of hand-set weights against their closed form, on inputs that
+    cross every ReLU cut (x < -1/2, -1/2 < x < 0, 0 < x < 1, x > 1) and give
+    negative logits.  Catches ReLU after layer 4, no ReLU after layer 2 or
+    3, a bias added after the ReLU instead of before, and a reversed tap."""
+    x = np.array([-2.0, -0.75, -0.25, 0.0, 0.3, 0.9, 1.5, 3.0, -1.2, 0.6, 2.2, -0.4])
+    logits, _ = cnn.forward(hand_set_params(), x)
+    want = closed_form_logits(x)
+    assert want.min() < 0 and want.max() > 0
+    np.testing.assert_allclose(logits, want, rtol=0, atol=1e-12)
