@@ -144,6 +144,36 @@ ispl_status ispl_find_plasma_line_gates(ispl_ctx* ctx, const float* spectra, int
                                         float* peak_power, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as ispl_integrate_spectra on a context created from *cfg, with
+ * no context and no allocation at all.
+ *   cfg       as for ispl_create (validated on every call; max_pulses bounds
+ *             n_pulses as it does for a context).
+ *   samples, tx_code, tx_per_pulse, n_pulses, spectra, accumulate, stream:
+ *             as for ispl_integrate_spectra (caller-owned device buffers).
+ * The twiddle table and the pulse-chunk partial spectra live in a static
+ * device array of ISPL_NOALLOC_SCRATCH_BYTES bytes (512 KiB of twiddles, 64
+ * MiB of partials) that the library holds on every GPU it runs on until the
+ * process ends; the table is rebuilt on `stream` by every call (one small
+ * launch).  The launch plan is ispl_create's automatic plan, whose partials
+ * never exceed 64 MiB (fewer than four workgroup slots of the chip per chunk
+ * row); a plan that needed more would be rejected with ISPL_ERR_UNSUPPORTED
+ * before anything is queued.  Results equal those of ispl_integrate_spectra
+ * (the same plan, the same kernels).  Every call on one GPU shares that GPU's
+ * array, which keeps the last call's contents: calls that overlap on one GPU
+ * (on different streams, or from different threads) race and give wrong
+ * results.  The first call on a device looks up its copy of the array
+ * (hipGetSymbolAddress); it never calls hipMalloc or hipFree.
+ */
+#define ISPL_NOALLOC_SCRATCH_BYTES ((64 << 20) + (512 << 10))
+
+ispl_status ispl_integrate_spectra_noalloc(const ispl_config* cfg, const void* samples,
+                                           const float* tx_code, int32_t tx_per_pulse,
+                                           int32_t n_pulses, float* spectra, int32_t accumulate,
+                                           void* stream);
+
+/*
  * Zoom DFT on the matrix cores: K bins of the N-point spectrum of every gate,
  * starting at a per-gate bin, without the full transform.  Each gate's
  * decoded rows are shifted so that its window starts at bin 0 and multiplied

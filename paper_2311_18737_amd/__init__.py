@@ -28,7 +28,7 @@ from ._lib import (  # noqa: F401
 def __getattr__(name):
     # torch-dependent pieces load lazily so the ABI can be inspected without torch
     if name in ("Context", "Zoom", "Net", "LearnedZoom", "StreamIngest", "Batch", "make_config",
-                "plan"):
+                "plan", "integrate_spectra_noalloc"):
         from . import context
 
         return getattr(context, name)

@@ -22,6 +22,8 @@ ISPL_SAMPLES_CI16 = 1
 ISPL_ZOOM_BF16X3 = 0
 ISPL_ZOOM_FP16X3 = 1
 
+ISPL_NOALLOC_SCRATCH_BYTES = (64 << 20) + (512 << 10)
+
 ISPL_NET_LEN = 1024
 ISPL_NET_PARAMS = 14881
 ISPL_NET_FP32 = 0
@@ -44,6 +46,7 @@ EXPORTED = (
     "ispl_net_loss_grad",
     "ispl_net_train_step",
     "ispl_integrate_spectra_gates",
+    "ispl_integrate_spectra_noalloc",
     "ispl_find_plasma_line_gates",
     "ispl_zoom_spectra_gates",
     "ispl_zoom_find_peaks",
@@ -185,6 +188,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ispl_net_train_step.restype = i32
     lib.ispl_integrate_spectra_gates.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, i32, vp]
     lib.ispl_integrate_spectra_gates.restype = i32
+    lib.ispl_integrate_spectra_noalloc.argtypes = [ctypes.POINTER(IsplConfig), vp, vp, i32, i32,
+                                                    vp, i32, vp]
+    lib.ispl_integrate_spectra_noalloc.restype = i32
     lib.ispl_find_plasma_line_gates.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
     lib.ispl_find_plasma_line_gates.restype = i32
     lib.ispl_zoom_spectra_gates.argtypes = [vp, vp, vp, i32, i32, vp, vp, vp, vp, i32, vp]

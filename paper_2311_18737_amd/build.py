@@ -16,8 +16,8 @@ CSRC = os.path.join(PKG_DIR, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_DIR = os.path.join(PKG_DIR, "lib")
 LIB_PATH = os.path.join(LIB_DIR, "libispl.so")
-SOURCES = ["ispl_kernels.hip", "ispl_zoom.hip", "ispl_cnn.hip", "ispl_lzoom.hip", "ispl_api.cpp",
-           "ispl_stream.cpp"]
+SOURCES = ["ispl_kernels.hip", "ispl_zoom.hip", "ispl_cnn.hip", "ispl_lzoom.hip", "ispl_noalloc.hip",
+           "ispl_api.cpp", "ispl_stream.cpp"]
 ARCH = "gfx950"
 
 

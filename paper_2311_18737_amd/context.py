@@ -205,6 +205,49 @@ class Context:
         return out_bins, (out_power if want_power else None)
 
 
+def integrate_spectra_noalloc(samples: torch.Tensor, tx: torch.Tensor, out: torch.Tensor, *,
+                              code_len: int, fft_len: int, n_gates: int, gate_step: int = 25,
+                              first_gate: int = 0, pulse_stride: Optional[int] = None,
+                              sample_type: str = "c64", max_pulses: Optional[int] = None,
+                              device: int = 0, accumulate: bool = False,
+                              stream=None) -> torch.Tensor:
+    """ispl_integrate_spectra_noalloc: the integration of Context.integrate_spectra
+    without a context; the library allocates nothing (its twiddle table and
+    chunk partials live in a static device array).  `out` (float32 [G][N]) is
+    required, so that the call queues kernels only."""
+    lib = load_library()
+    dev = torch.device("cuda", device)
+    _require(samples.device == dev and samples.is_contiguous(), f"samples must be contiguous on {dev}")
+    n_pulses = samples.shape[0]
+    cfg = make_config(code_len=code_len, fft_len=fft_len, n_gates=n_gates, gate_step=gate_step,
+                      first_gate=first_gate, pulse_stride=pulse_stride, sample_type=sample_type,
+                      max_pulses=max(1, n_pulses) if max_pulses is None else max_pulses,
+                      device=device)
+    if sample_type == "c64":
+        _require(samples.dtype == torch.complex64 and samples.dim() == 2,
+                 "c64 samples must be complex64 [n_pulses][pulse_stride]")
+    else:
+        _require(samples.dtype == torch.int16 and samples.dim() == 3 and samples.shape[2] == 2,
+                 "ci16 samples must be int16 [n_pulses][pulse_stride][2]")
+    _require(samples.shape[1] == cfg.pulse_stride,
+             f"samples rows must hold pulse_stride={cfg.pulse_stride} samples")
+    _require(tx.device == dev and tx.is_contiguous() and tx.dtype == torch.complex64,
+             "tx must be contiguous complex64 on the device")
+    if tx.dim() == 1:
+        tx = tx.unsqueeze(0)
+    _require(tx.dim() == 2 and tx.shape[1] == code_len, "tx must be [P or 1][code_len]")
+    per_pulse = tx.shape[0] != 1
+    _require(not per_pulse or tx.shape[0] == n_pulses, "tx rows must be 1 or n_pulses")
+    _require(out.device == dev and out.dtype == torch.float32 and out.is_contiguous()
+             and tuple(out.shape) == (n_gates, fft_len),
+             "out must be contiguous float32 [n_gates][fft_len] on the device")
+    st = lib.ispl_integrate_spectra_noalloc(
+        ctypes.byref(cfg), _ptr(samples), _ptr(tx), int(per_pulse), n_pulses, _ptr(out),
+        int(bool(accumulate)), ctypes.c_void_p(_stream_handle(stream, dev)))
+    check(st, "ispl_integrate_spectra_noalloc")
+    return out
+
+
 _ZOOM_PRECISIONS = {"bf16x3": _lib.ISPL_ZOOM_BF16X3, "fp16x3": _lib.ISPL_ZOOM_FP16X3}
 
 

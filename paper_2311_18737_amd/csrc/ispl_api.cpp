@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <string>
 #include <vector>
@@ -346,6 +347,22 @@ ispl_status ispl_plan(const ispl_config* cfg, int32_t n_pulses, int32_t* chunks,
   return ok();
 }
 
+// The device exists and is a gfx950.
+static ispl_status check_device(int32_t device) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0)
+    return fail(ISPL_ERR_DEVICE, "no HIP device (%s)", hipGetErrorString(e));
+  if (device >= count) return fail(ISPL_ERR_DEVICE, "device %d of %d", device, count);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(ISPL_ERR_DEVICE, "device %d is %s; this library is built for gfx950", device,
+                prop.gcnArchName);
+  return ISPL_OK;
+}
+
 // A context whose automatic plans keep at least min_chunk_pulses pulses per
 // chunk (ispl_create: kMinChunkPulses).
 static ispl_status create_ctx(const ispl_config* cfg, int32_t min_chunk_pulses, ispl_ctx** out) {
@@ -354,20 +371,11 @@ static ispl_status create_ctx(const ispl_config* cfg, int32_t min_chunk_pulses, 
   ispl_status st = validate_config(cfg);
   if (st != ISPL_OK) return st;
 
-  int count = 0;
-  hipError_t e = hipGetDeviceCount(&count);
-  if (e != hipSuccess || count == 0)
-    return fail(ISPL_ERR_DEVICE, "no HIP device (%s)", hipGetErrorString(e));
-  if (cfg->device >= count)
-    return fail(ISPL_ERR_DEVICE, "device %d of %d", cfg->device, count);
-  hipDeviceProp_t prop;
-  e = hipGetDeviceProperties(&prop, cfg->device);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
-  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-    return fail(ISPL_ERR_DEVICE, "device %d is %s; this library is built for gfx950",
-                cfg->device, prop.gcnArchName);
+  st = check_device(cfg->device);
+  if (st != ISPL_OK) return st;
 
   DeviceGuard guard(cfg->device);
+  hipError_t e;
   ispl_ctx* ctx = new (std::nothrow) ispl_ctx{};
   if (!ctx) return fail(ISPL_ERR_OUT_OF_MEMORY, "host allocation");
   ctx->cfg = *cfg;
@@ -419,17 +427,11 @@ void ispl_destroy(ispl_ctx* ctx) {
   delete ctx;
 }
 
-// With deferred_chunks non-NULL a pulse-chunked plan leaves its partial
-// spectra in the context's scratch ([C][G][N]) instead of reducing them into
-// `spectra`; *deferred_chunks reports C (1: `spectra` holds the result).
-static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const float* tx_code,
-                                  int32_t tx_per_pulse, int32_t n_pulses,
-                                  const int32_t* gate_list, const int32_t* gate_count,
-                                  float* spectra, int32_t accumulate, void* stream,
-                                  int32_t* deferred_chunks = nullptr) {
-  if (deferred_chunks) *deferred_chunks = 1;
-  if (!ctx) return fail(ISPL_ERR_INVALID_ARG, "context is NULL");
-  const ispl_config& c = ctx->cfg;
+// Arguments of one integration against the geometry c (nothing is launched).
+static ispl_status check_integrate_args(const ispl_config& c, const void* samples,
+                                        const float* tx_code, int32_t tx_per_pulse,
+                                        int32_t n_pulses, const float* spectra,
+                                        int32_t accumulate) {
   if (n_pulses < 0 || n_pulses > c.max_pulses)
     return fail(ISPL_ERR_INVALID_ARG, "n_pulses %d outside [0, max_pulses %d]", n_pulses,
                 c.max_pulses);
@@ -445,6 +447,23 @@ static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const floa
   }
   if ((tx_per_pulse != 0 && tx_per_pulse != 1) || (accumulate != 0 && accumulate != 1))
     return fail(ISPL_ERR_INVALID_ARG, "tx_per_pulse and accumulate must be 0 or 1");
+  return ISPL_OK;
+}
+
+// With deferred_chunks non-NULL a pulse-chunked plan leaves its partial
+// spectra in the context's scratch ([C][G][N]) instead of reducing them into
+// `spectra`; *deferred_chunks reports C (1: `spectra` holds the result).
+static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const float* tx_code,
+                                  int32_t tx_per_pulse, int32_t n_pulses,
+                                  const int32_t* gate_list, const int32_t* gate_count,
+                                  float* spectra, int32_t accumulate, void* stream,
+                                  int32_t* deferred_chunks = nullptr) {
+  if (deferred_chunks) *deferred_chunks = 1;
+  if (!ctx) return fail(ISPL_ERR_INVALID_ARG, "context is NULL");
+  const ispl_config& c = ctx->cfg;
+  const ispl_status st =
+      check_integrate_args(c, samples, tx_code, tx_per_pulse, n_pulses, spectra, accumulate);
+  if (st != ISPL_OK) return st;
 
   DeviceGuard guard(c.device);
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -522,6 +541,55 @@ ispl_status ispl_integrate_spectra_gates(ispl_ctx* ctx, const void* samples,
   if (st != ISPL_OK) return st;
   return integrate_impl(ctx, samples, tx_code, tx_per_pulse, n_pulses, gate_list, gate_count,
                         spectra, accumulate, stream);
+}
+
+ispl_status ispl_integrate_spectra_noalloc(const ispl_config* cfg, const void* samples,
+                                           const float* tx_code, int32_t tx_per_pulse,
+                                           int32_t n_pulses, float* spectra, int32_t accumulate,
+                                           void* stream) {
+  ispl_status st = validate_config(cfg);
+  if (st != ISPL_OK) return st;
+  st = check_integrate_args(*cfg, samples, tx_code, tx_per_pulse, n_pulses, spectra, accumulate);
+  if (st != ISPL_OK) return st;
+  // the plan of a context created from cfg; its partials stay below 64 MiB
+  // (chunks x workgroups per chunk < 4 x the chip's workgroup slots), which
+  // the static array holds
+  const Plan pl = make_plan(*cfg, n_pulses > 0 ? n_pulses : 1);
+  const int64_t row_bytes = static_cast<int64_t>(cfg->n_gates) * cfg->fft_len * 4;
+  if (pl.chunks > 1 &&
+      pl.chunks * row_bytes > static_cast<int64_t>(ispl::NOALLOC_PARTIAL_BYTES))
+    return fail(ISPL_ERR_UNSUPPORTED,
+                "plan needs %lld bytes of chunk partials; the static scratch holds %zu",
+                static_cast<long long>(pl.chunks * row_bytes), ispl::NOALLOC_PARTIAL_BYTES);
+  if (static_cast<size_t>(cfg->fft_len) * 8 > ispl::NOALLOC_TWIDDLE_BYTES)
+    return fail(ISPL_ERR_UNSUPPORTED, "fft_len %d: twiddle table exceeds the static scratch",
+                cfg->fft_len);
+  // the gfx950 check once per device (device properties are not cheap)
+  static std::atomic<int> checked[64];
+  if (cfg->device >= 64) return fail(ISPL_ERR_UNSUPPORTED, "device %d >= 64", cfg->device);
+  if (checked[cfg->device].load(std::memory_order_acquire) == 0) {
+    st = check_device(cfg->device);
+    if (st != ISPL_OK) return st;
+    checked[cfg->device].store(1, std::memory_order_release);
+  }
+  DeviceGuard guard(cfg->device);
+  unsigned char* base = nullptr;
+  hipError_t e = ispl::noalloc_scratch(cfg->device, &base);
+  if (e != hipSuccess) return hip_fail(e, "static scratch lookup");
+  // a context on the stack whose tables are the static array's regions
+  ispl_ctx tmp{};
+  tmp.cfg = *cfg;
+  tmp.chunks_max = pl.chunks;
+  tmp.twiddle = reinterpret_cast<float*>(base);
+  tmp.partial = pl.chunks > 1 ? reinterpret_cast<float*>(base + ispl::NOALLOC_TWIDDLE_BYTES)
+                              : nullptr;
+  tmp.min_chunk_pulses = kMinChunkPulses;
+  if (n_pulses > 0) {
+    e = ispl::launch_build_twiddles(tmp.twiddle, cfg->fft_len, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "twiddle launch");
+  }
+  return integrate_impl(&tmp, samples, tx_code, tx_per_pulse, n_pulses, nullptr, nullptr, spectra,
+                        accumulate, stream);
 }
 
 ispl_status ispl_zoom_create(ispl_ctx* ctx, int32_t n_bins, int32_t precision,

@@ -58,6 +58,16 @@ hipError_t launch_reduce_chunks(const float* partial, float* spectra, int64_t el
                                 int32_t chunks, int32_t accumulate, int32_t n_fft,
                                 const int32_t* list, const int32_t* count, hipStream_t stream);
 
+// Static scratch of ispl_integrate_spectra_noalloc: twiddle table first, the
+// chunk partials after it.
+constexpr size_t NOALLOC_TWIDDLE_BYTES = size_t{512} << 10;  // N <= 65536 complex64
+constexpr size_t NOALLOC_PARTIAL_BYTES = ISPL_NOALLOC_SCRATCH_BYTES - NOALLOC_TWIDDLE_BYTES;
+// This GPU's copy of the array (`device` must be current); looked up once per
+// device.
+hipError_t noalloc_scratch(int device, unsigned char** base);
+// W_N^i, i < n_fft, into `table` (complex64 pairs), as the context builds it.
+hipError_t launch_build_twiddles(float* table, int32_t n_fft, hipStream_t stream);
+
 hipError_t launch_fill_zero(float* dst, int64_t elems, hipStream_t stream);
 hipError_t launch_fill_zero_rows(float* dst, int32_t n_gates, int32_t n_fft, const int32_t* list,
                                  const int32_t* count, hipStream_t stream);

@@ -120,6 +120,17 @@ static void plain_path(const Shape& s) {
         ISPL_ERR_INVALID_ARG);
   CHECK(ispl_integrate_spectra_gates(ctx, io.samples, io.tx, 1, s.P, nullptr, io.count,
                                      io.spectra, 0, nullptr) == ISPL_ERR_INVALID_ARG);
+  // the same integrations without a context: static scratch only
+  for (int P : {s.P, 1, 0}) {
+    CHECK(ispl_integrate_spectra_noalloc(&c, io.samples, io.tx, 1, P, io.spectra, 0, nullptr) ==
+          ISPL_OK);
+    CHECK(ispl_integrate_spectra_noalloc(&c, io.samples, io.tx1, 0, P, io.spectra, 1, nullptr) ==
+          ISPL_OK);
+  }
+  CHECK(ispl_integrate_spectra_noalloc(&c, io.samples, io.tx, 1, s.P + 1, io.spectra, 0,
+                                       nullptr) == ISPL_ERR_INVALID_ARG);
+  CHECK(ispl_integrate_spectra_noalloc(nullptr, io.samples, io.tx, 1, s.P, io.spectra, 0,
+                                       nullptr) == ISPL_ERR_INVALID_ARG);
   int32_t chunks = 0, waves = 0, blocks = 0;
   CHECK(ispl_plan(&c, s.P, &chunks, &waves, &blocks) == ISPL_OK);
   CHECK(chunks >= 1 && waves >= 1 && blocks >= 1);

@@ -375,6 +375,25 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t st) {
   });
   return hipSuccess;
 }
+// The static array of the entry point that allocates nothing: one host block
+// that stays registered (the library never frees it).
+hipError_t noalloc_scratch(int device, unsigned char** base) {
+  static unsigned char* block = nullptr;
+  if (device != 0) return hipErrorInvalidDevice;
+  if (!block) {
+    block = static_cast<unsigned char*>(malloc(ISPL_NOALLOC_SCRATCH_BYTES));
+    g_allocs[reinterpret_cast<uintptr_t>(block)] = ISPL_NOALLOC_SCRATCH_BYTES;
+  }
+  *base = block;
+  return hipSuccess;
+}
+hipError_t launch_build_twiddles(float* table, int32_t n_fft, hipStream_t st) {
+  run_on(st, [=] {
+    if (n_fft < 1 || size_t(n_fft) * 8 > NOALLOC_TWIDDLE_BYTES) mock_fail("twiddle table size");
+    check_range(table, size_t(n_fft) * 8, "twiddle table");
+  });
+  return hipSuccess;
+}
 hipError_t launch_reduce_chunks(const float* partial, float* spectra, int64_t elems, int32_t chunks,
                                 int32_t, int32_t n_fft, const int32_t* list, const int32_t* count,
                                 hipStream_t st) {
