@@ -307,10 +307,15 @@ ispl_status ispl_net_select(ispl_net* net, const float* logits, int32_t n_gates,
  *   3. ispl_net_select with (cfg->fft_len, window_bins, threshold);
  *   4. ispl_zoom_spectra_gates over the zoomed gates (window_bins bins from
  *      bin_start, zoom_precision) and ispl_integrate_spectra_gates at
- *      cfg->fft_len over the fallback gates;
+ *      cfg->fft_len over the fallback gates -- the latter with its pulses
+ *      split into as many chunks as the number k of fallback gates leaves
+ *      room for (k x chunks workgroups fill the chip once; at most 64 chunks
+ *      of at least 8 pulses), chosen on the device from k, so that a few
+ *      fallback gates cost a small part of a full integration;
  *   5. ispl_zoom_find_peaks and ispl_find_plasma_line_gates (full band).
- * Given the coarse spectra of step 1, steps 2-5 equal those calls bit for
- * bit.
+ * Given the coarse spectra of step 1, steps 2, 3 and the zoomed gates' part
+ * of steps 4-5 equal those calls bit for bit; the fallback rows equal
+ * ispl_integrate_spectra_gates' up to the order of the pulse sum.
  * peak_bin[g] / peak_power[g] (device int32 / float [n_gates]; peak_power
  * may be NULL) then hold every gate's line bin at N = cfg->fft_len.
  * ispl_lzoom_create: cfg as for ispl_create with code_len <= 1024 and
@@ -318,8 +323,9 @@ ispl_status ispl_net_select(ispl_net* net, const float* logits, int32_t n_gates,
  * window_bins <= fft_len; zoom_precision an ispl_zoom_precision; threshold
  * in (0, 1].  `net` stays owned by the caller, must outlive the object and
  * be on cfg->device; its current parameters are used at every call.  The
- * object owns two contexts, a zoom table and [n_gates] x (2 * 1024 +
- * window_bins + fft_len) floats of buffers.  Not thread-safe, and calls on
+ * object owns two contexts, a zoom table, [n_gates] x (2 * 1024 +
+ * window_bins + fft_len) floats of buffers and up to 16 MiB of fallback
+ * chunk partials.  Not thread-safe, and calls on
  * one object must not overlap on different streams (it owns the scratch and
  * the decision's completion counter).  Capturable in a HIP graph (it neither
  * allocates nor synchronises).
@@ -371,19 +377,21 @@ void ispl_destroy(ispl_ctx* ctx);
  *                       on first use and again when io, accumulate or the plan
  *                       change); use_graph = 0 queues the modes' launches on
  *                       `stream` one after another (a caller may capture that).
+ *                       A replaced graph is kept until the device has been
+ *                       synchronised (a launch of it may still be running):
+ *                       every eighth re-capture synchronises the device once
+ *                       and frees the replaced graphs.
  *   ispl_batch_tune     the autotuner: coordinate descent over each mode's
  *                       waves per workgroup (bin classes a workgroup computes:
  *                       the tile shape) and pulse chunks, heaviest mode first,
  *                       then parallel vs serial branches and the order; each
- *                       candidate is the graph's median time over `trials`
- *                       runs on an internal stream.  Keeps and returns the
- *                       fastest plan and its time (either pointer may be
- *                       NULL).  It writes the spectra of io.  Builds
- *                       without ISPL_BATCH_TUNER defined (the default) return
- *                       ISPL_ERR_UNSUPPORTED after the argument checks: the
- *                       tuner is switched off until a host-side crash seen
- *                       while it ran is explained; set_plan still applies
- *                       hand-chosen plans.
+ *                       candidate is the median time over `trials` runs of
+ *                       its launches, queued in the plan's branch shape on the
+ *                       object's own streams (the graph of the chosen plan is
+ *                       captured by the next ispl_batch_integrate).  Keeps and
+ *                       returns the fastest plan and its time (either pointer
+ *                       may be NULL).  It writes the spectra of io and blocks
+ *                       until its runs are done.
  *   ispl_batch_get_plan / set_plan  the plan in use (waves 0 and chunks 0 mean
  *                       the automatic choice; waves only for modes with
  *                       L <= 1024: a power of two <= min(16, N/1024)).

@@ -692,9 +692,8 @@ class Batch:
         return res
 
     def tune(self, inputs, outs=None, trials: int = 3):
-        """Autotune the plan on these inputs (writes their spectra); returns
-        (plan dict, best ms).  Raises IsplError (ISPL_ERR_UNSUPPORTED) in
-        builds where the library's autotuner is switched off."""
+        """Autotune the plan on these inputs (writes their spectra, blocks
+        until the tuning runs are done); returns (plan dict, best ms)."""
         io, _ = self._io(inputs, outs)
         plan = _lib.IsplBatchPlan()
         ms = ctypes.c_float()

@@ -450,15 +450,47 @@ static ispl_status check_integrate_args(const ispl_config& c, const void* sample
   return ISPL_OK;
 }
 
+// Adaptive chunking of a gate-list launch (see ispl::FusedArgs): partial rows
+// by list slot in `partial` ([rows][N]); the chunk count follows from the
+// device-side list length, so the partials are always left for the caller to
+// sum (ispl::launch_split_peaks does).
+struct AdaptiveFallback {
+  float* partial;
+  int32_t target, max_chunks, rows;
+};
+
+// The adaptive parameters for a context's fallback launches over n_pulses: at
+// most one round of the chip, at most 64 chunks (the reduction reads each
+// chunk's row) of at least kMinChunkPulses pulses.
+static AdaptiveFallback adaptive_plan(const ispl_config& c, int32_t n_pulses, float* partial) {
+  const Plan pl = make_plan(c, n_pulses > 0 ? n_pulses : 1);
+  int per_cu = kLdsPerCu / ispl::fused_lds_bytes(pl.rw, pl.sub_len);
+  if (per_cu * pl.rw > kMaxWavesPerCu) per_cu = kMaxWavesPerCu / pl.rw;
+  if (per_cu < 1) per_cu = 1;
+  AdaptiveFallback f{};
+  f.partial = partial;
+  f.target = kComputeUnits * per_cu;
+  f.rows = f.target / pl.zgroups;
+  f.max_chunks = std::max(1, std::min(64, n_pulses / kMinChunkPulses));
+  return f;
+}
+
+static int32_t adaptive_zgroups(const ispl_config& c) { return make_plan(c, 1).zgroups; }
+
 // With deferred_chunks non-NULL a pulse-chunked plan leaves its partial
 // spectra in the context's scratch ([C][G][N]) instead of reducing them into
 // `spectra`; *deferred_chunks reports C (1: `spectra` holds the result).
+// With `adapt` (gate lists only) the chunking is adaptive and its partials
+// are always left in adapt->partial (*deferred_chunks = 0).
 static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const float* tx_code,
                                   int32_t tx_per_pulse, int32_t n_pulses,
                                   const int32_t* gate_list, const int32_t* gate_count,
                                   float* spectra, int32_t accumulate, void* stream,
-                                  int32_t* deferred_chunks = nullptr) {
+                                  int32_t* deferred_chunks = nullptr,
+                                  const AdaptiveFallback* adapt = nullptr) {
   if (deferred_chunks) *deferred_chunks = 1;
+  if (adapt && (!gate_list || !deferred_chunks || accumulate))
+    return fail(ISPL_ERR_INVALID_ARG, "internal: adaptive chunking needs a list and no accumulate");
   if (!ctx) return fail(ISPL_ERR_INVALID_ARG, "context is NULL");
   const ispl_config& c = ctx->cfg;
   const ispl_status st =
@@ -504,8 +536,20 @@ static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const floa
   a.waves_per_block = pl.rw;
   a.gate_list = gate_list;
   a.gate_count = gate_count;
+  if (adapt) {
+    a.out = spectra;
+    a.chunks = 1;
+    a.adapt_partial = adapt->partial;
+    a.adapt_target = adapt->target;
+    a.adapt_max_chunks = adapt->max_chunks;
+    a.adapt_rows = adapt->rows;
+  }
   e = ispl::launch_fused(a, s);
   if (e != hipSuccess) return hip_fail(e, "fused launch");
+  if (adapt) {
+    *deferred_chunks = 0;
+    return ok();
+  }
   if (pl.chunks > 1) {
     if (deferred_chunks && !accumulate) {
       *deferred_chunks = pl.chunks;
@@ -1057,6 +1101,9 @@ struct ispl_lzoom {
   int32_t* fallback_list; // [G]
   int32_t* counts;        // [2]: zoomed, fallback
   int32_t* done;          // completion counter of the decision (zero between calls)
+  int32_t* fb_slot;       // [G]: position of each fallback gate in the fallback list
+  float* fb_partial;      // [fb_rows][N]: chunk partials of the fallback launch
+  int32_t fb_rows;
 };
 
 namespace {
@@ -1064,7 +1111,7 @@ namespace {
 void lzoom_free(ispl_lzoom* z) {
   void* bufs[] = {z->coarse_spectra, z->logits, z->confidence, z->window_spectra,
                   z->full_spectra, z->bin_start, z->flag, z->zoom_list, z->fallback_list,
-                  z->counts, z->done};
+                  z->counts, z->done, z->fb_slot, z->fb_partial};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (z->zoom) ispl_zoom_destroy(z->zoom);
@@ -1102,7 +1149,9 @@ ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t win
   // the coarse transforms are short: chunks of 4 pulses give enough waves to
   // fill the chip on small workloads, and the network sums the partials
   st = create_ctx(&cc, 4, &z->coarse);
-  if (st == ISPL_OK) st = ispl_create(cfg, &z->fine);
+  // the fine context runs only the fallback, whose chunking is adaptive and
+  // whose partials live in the object's own buffer: no scratch of its own
+  if (st == ISPL_OK) st = create_ctx(cfg, INT32_MAX, &z->fine);
   if (st == ISPL_OK) st = ispl_zoom_create(z->fine, window_bins, zoom_precision, &z->zoom);
   if (st != ISPL_OK) {
     const std::string why = g_last_error;
@@ -1112,6 +1161,7 @@ ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t win
   }
   DeviceGuard guard(cfg->device);
   const int64_t G = cfg->n_gates;
+  z->fb_rows = adaptive_plan(*cfg, cfg->max_pulses, nullptr).rows;
   struct {
     void** p;
     int64_t bytes;
@@ -1125,7 +1175,9 @@ ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t win
               {reinterpret_cast<void**>(&z->zoom_list), 4 * G},
               {reinterpret_cast<void**>(&z->fallback_list), 4 * G},
               {reinterpret_cast<void**>(&z->counts), 8},
-              {reinterpret_cast<void**>(&z->done), 4}};
+              {reinterpret_cast<void**>(&z->done), 4},
+              {reinterpret_cast<void**>(&z->fb_slot), 4 * G},
+              {reinterpret_cast<void**>(&z->fb_partial), int64_t{4} * z->fb_rows * cfg->fft_len}};
   for (auto& w : want) {
     const hipError_t e = hipMalloc(w.p, static_cast<size_t>(w.bytes));
     if (e != hipSuccess) {
@@ -1196,7 +1248,8 @@ ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx
     pe.n_pulses = fp16 ? n_pulses : 0;
     e = ispl::launch_select_and_exponents(z->logits, G, c.fft_len, z->window_bins, z->threshold,
                                           z->bin_start, z->confidence, z->flag, z->zoom_list,
-                                          z->fallback_list, z->counts, z->done, pe, s);
+                                          z->fallback_list, z->counts, z->done, z->fb_slot, pe,
+                                          s);
   }
   if (e != hipSuccess) return hip_fail(e, "learned-zoom network launch");
   // zoomed gates: K bins around the proposed centre; the others: full spectra;
@@ -1204,12 +1257,26 @@ ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx
   st = zoom_impl(z->zoom, samples, tx_code, tx_per_pulse, n_pulses, z->bin_start, z->zoom_list,
                  z->counts, z->window_spectra, 0, stream, &zoom_chunks, true);
   if (st != ISPL_OK) return st;
+  // the fallback's pulse chunks follow from the device-side number of
+  // fallback gates: few gates take many chunks and still fill the chip
+  const AdaptiveFallback fb = adaptive_plan(c, n_pulses, z->fb_partial);
+  if (fb.rows > z->fb_rows)
+    return fail(ISPL_ERR_INVALID_ARG, "internal: fallback plan needs %d rows > %d", fb.rows,
+                z->fb_rows);
   st = integrate_impl(z->fine, samples, tx_code, tx_per_pulse, n_pulses, z->fallback_list,
-                      z->counts + 1, z->full_spectra, 0, stream, &fine_chunks);
+                      z->counts + 1, z->full_spectra, 0, stream, &fine_chunks, &fb);
   if (st != ISPL_OK) return st;
+  ispl::FallbackChunks fc{};
+  fc.counts = z->counts;
+  fc.slot = z->fb_slot;
+  fc.partial = z->fb_partial;
+  fc.zgroups = adaptive_zgroups(c);
+  fc.target = fb.target;
+  fc.max_chunks = fb.max_chunks;
+  fc.rows = fb.rows;
   e = ispl::launch_split_peaks(z->window_spectra, z->zoom->partial, zoom_chunks, z->full_spectra,
-                               z->fine->partial, fine_chunks, z->flag, z->bin_start, G,
-                               z->window_bins, c.fft_len, peak_bin, peak_power, s);
+                               fc, z->flag, z->bin_start, G, z->window_bins, c.fft_len, peak_bin,
+                               peak_power, s);
   if (e != hipSuccess) return hip_fail(e, "learned-zoom peak launch");
   return ok();
 }
@@ -1248,12 +1315,23 @@ struct ispl_batch {
   int32_t cached_acc;
   hipGraphExec_t exec;
   bool graph_valid;
+  // Executable graphs replaced by a new capture.  A launch of one may still be
+  // in the runtime's hands (its completion bookkeeping can outlive the events
+  // that follow it), so they are destroyed only after a device-wide
+  // synchronisation: when kMaxRetired have gathered, or with the object.
+  hipGraphExec_t retired[8];
+  int32_t n_retired;
 };
 
 namespace {
 
+constexpr int kMaxRetired = 8;
+
+// The caller has synchronised the device (or no graph was ever launched).
 void batch_free(ispl_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  for (int i = 0; i < b->n_retired; ++i) (void)hipGraphExecDestroy(b->retired[i]);
+  b->n_retired = 0;
   for (int i = 0; i < b->n_modes; ++i) {
     if (b->branch[i]) (void)hipStreamDestroy(b->branch[i]);
     if (b->join[i]) (void)hipEventDestroy(b->join[i]);
@@ -1289,10 +1367,17 @@ ispl_status batch_run(ispl_batch* b, const ispl_batch_io* io, int32_t accumulate
 // or one after another in plan order, then instantiates the graph.
 ispl_status batch_capture(ispl_batch* b, const ispl_batch_io* io, int32_t accumulate) {
   // until a new graph is instantiated there is none to replay, also after a
-  // failed capture
+  // failed capture; the old executable is retired, never destroyed while a
+  // launch of it may be in flight
   b->graph_valid = false;
   if (b->exec) {
-    (void)hipGraphExecDestroy(b->exec);
+    if (b->n_retired == kMaxRetired) {
+      const hipError_t se = hipDeviceSynchronize();
+      if (se != hipSuccess) return hip_fail(se, "batch: synchronise before freeing old graphs");
+      for (int i = 0; i < b->n_retired; ++i) (void)hipGraphExecDestroy(b->retired[i]);
+      b->n_retired = 0;
+    }
+    b->retired[b->n_retired++] = b->exec;
     b->exec = nullptr;
   }
   hipGraph_t g = nullptr;
@@ -1324,6 +1409,29 @@ ispl_status batch_capture(ispl_batch* b, const ispl_batch_io* io, int32_t accumu
   for (int m = 0; m < b->n_modes; ++m) b->cached[m] = io[m];
   b->cached_acc = accumulate;
   b->graph_valid = true;
+  return ISPL_OK;
+}
+
+// The modes' launches queued eagerly in the plan's shape: on the object's
+// parallel branches (fork and join events on `s`, as the graph's branches) or
+// one after another on `s`.
+ispl_status batch_launch_eager(ispl_batch* b, const ispl_batch_io* io, int32_t accumulate,
+                               hipStream_t s) {
+  if (b->plan.serial) return batch_run(b, io, accumulate, s);
+  hipError_t e = hipEventRecord(b->fork, s);
+  ispl_status st = ISPL_OK;
+  for (int k = 0; k < b->n_modes && e == hipSuccess && st == ISPL_OK; ++k) {
+    const int m = b->plan.order[k];
+    e = hipStreamWaitEvent(b->branch[m], b->fork, 0);
+    if (e != hipSuccess) break;
+    st = integrate_impl(b->ctx[m], io[m].samples, io[m].tx_code, io[m].tx_per_pulse,
+                        io[m].n_pulses, nullptr, nullptr, io[m].spectra, accumulate,
+                        b->branch[m]);
+    const hipError_t je = hipEventRecord(b->join[m], b->branch[m]);
+    e = je == hipSuccess ? hipStreamWaitEvent(s, b->join[m], 0) : je;
+  }
+  if (st != ISPL_OK) return st;
+  if (e != hipSuccess) return hip_fail(e, "batch branches");
   return ISPL_OK;
 }
 
@@ -1450,29 +1558,25 @@ ispl_status ispl_batch_tune(ispl_batch* b, const ispl_batch_io* io, int32_t tria
   if (!b || !io) return fail(ISPL_ERR_INVALID_ARG, "batch or io is NULL");
   if (trials < 1 || trials > 100)
     return fail(ISPL_ERR_INVALID_ARG, "trials %d outside [1, 100]", trials);
-#ifndef ISPL_BATCH_TUNER
-  // Switched off: a process running the tuner ended in a host-side crash whose
-  // cause is not known yet.  Plans can still be set by hand (ispl_batch_set_plan).
-  (void)best;
-  (void)best_ms;
-  return fail(ISPL_ERR_UNSUPPORTED, "the batch autotuner is switched off in this build");
-#else
   DeviceGuard guard(b->device);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   if (e != hipSuccess) return hip_fail(e, "tune events");
   hipStream_t s = b->cap;
-  // median time of the batch under a plan, launched from its graph
+  // median time of the batch under a plan, its launches queued eagerly in the
+  // plan's shape on the object's own streams (no graph per candidate: the
+  // graph of the chosen plan is captured once, by the next ispl_batch_integrate)
   auto measure = [&](const ispl_batch_plan& p, float* ms) -> ispl_status {
     b->plan = p;
     apply_plan(b);
-    ispl_status st = batch_capture(b, io, 0);
-    if (st != ISPL_OK) return st;
     std::vector<float> t;
     for (int r = 0; r <= trials; ++r) {
       hipError_t ee = hipEventRecord(e0, s);
-      if (ee == hipSuccess) ee = hipGraphLaunch(b->exec, s);
+      if (ee == hipSuccess) {
+        const ispl_status st = batch_launch_eager(b, io, 0, s);
+        if (st != ISPL_OK) return st;
+      }
       if (ee == hipSuccess) ee = hipEventRecord(e1, s);
       if (ee == hipSuccess) ee = hipEventSynchronize(e1);
       float x = 0.f;
@@ -1551,7 +1655,6 @@ ispl_status ispl_batch_tune(ispl_batch* b, const ispl_batch_io* io, int32_t tria
   if (best) *best = cur;
   if (best_ms) *best_ms = cur_ms;
   return ok();
-#endif
 }
 
 }  // extern "C"

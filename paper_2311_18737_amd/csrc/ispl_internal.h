@@ -20,6 +20,27 @@ ispl_status report(ispl_status s, const char* msg);
 constexpr int SUB = 1024;
 constexpr int MAX_WAVES_PER_BLOCK = 16;
 
+#if defined(__HIP__)
+#define ISPL_HOST_DEVICE __host__ __device__
+#else
+#define ISPL_HOST_DEVICE
+#endif
+
+// Pulse chunks of a gate-list launch whose list length k is only known on the
+// device: as many chunks as keep k x zgroups x chunks workgroups within one
+// round of the chip (`target` workgroup slots), at most max_chunks and at most
+// rows / k (partial rows available), at least one.  The host sizes the grid
+// and the partial buffer with the same rule, the kernels and the partial
+// reduction derive the chunk count from the device-side k.
+ISPL_HOST_DEVICE inline int adaptive_chunks(int k, int zgroups, int target, int max_chunks,
+                                            int rows) {
+  if (k <= 0) return 1;
+  int c = target / (k * zgroups);
+  if (c > max_chunks) c = max_chunks;
+  if (c > rows / k) c = rows / k;
+  return c > 1 ? c : 1;
+}
+
 // Geometry and plan of one fused launch.
 struct FusedArgs {
   const void* samples;     // [P][stride] ci16 or c64
@@ -42,6 +63,15 @@ struct FusedArgs {
   int32_t waves_per_block; // RW in {1, 2, 4, 8, 16} (16 when M = 16 SUB)
   const int32_t* gate_list;  // optional: work on gate_list[i], i < *gate_count, only
   const int32_t* gate_count; // device int32, read by the kernels
+  // Adaptive chunking (gate lists only; adapt_target 0 = off): the chunk count
+  // is adaptive_chunks(*gate_count, R / RW, adapt_target, adapt_max_chunks,
+  // adapt_rows) and `chunks` is not read.  With one chunk `out` receives the
+  // rows as usual; with more, chunk c of list slot i goes to row c * k + i of
+  // adapt_partial ([adapt_rows][N]).
+  float* adapt_partial;
+  int32_t adapt_target;
+  int32_t adapt_max_chunks;
+  int32_t adapt_rows;
 };
 
 constexpr int MAX_BATCH_MODES = 8;
@@ -156,11 +186,20 @@ hipError_t launch_select_windows(const float* logits, int32_t n_gates, int32_t f
 // zoom_chunks or fine_chunks > 1 the rows are first summed from the chunk
 // partials ([C][G][len], ascending c) and written to window_spectra /
 // full_spectra.
+// Adaptive chunking of the fallback launch (see FusedArgs): the fallback
+// list length counts[1], the slot of each fallback gate in that list, and the
+// rule's parameters.
+struct FallbackChunks {
+  const int32_t* counts;  // [2]: zoomed, fallback
+  const int32_t* slot;    // [G]: position of a fallback gate in the fallback list
+  const float* partial;   // [rows][N]
+  int32_t zgroups, target, max_chunks, rows;
+};
 hipError_t launch_split_peaks(float* window_spectra, const float* window_partial,
-                              int32_t zoom_chunks, float* full_spectra, const float* full_partial,
-                              int32_t fine_chunks, const int32_t* flag, const int32_t* bin_start,
-                              int32_t n_gates, int32_t window_bins, int32_t fine_len,
-                              int32_t* peak_bin, float* peak_power, hipStream_t s);
+                              int32_t zoom_chunks, float* full_spectra, const FallbackChunks& fb,
+                              const int32_t* flag, const int32_t* bin_start, int32_t n_gates,
+                              int32_t window_bins, int32_t fine_len, int32_t* peak_bin,
+                              float* peak_power, hipStream_t s);
 // Per-pulse FP16 exponents of the zoom DFT (pulses 0 .. n_pulses - 1).
 struct PulseExpArgs {
   const void* samples;
@@ -170,11 +209,13 @@ struct PulseExpArgs {
   int32_t sample_type, code_len, tx_per_pulse, n_pulses;
 };
 // select_windows and, in the same launch, the pulse exponents (n_pulses = 0: none).
+// fb_slot (device int32 [n_gates]) receives each fallback gate's position in
+// the fallback list (-1 for zoomed gates).
 hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int32_t fine_len,
                                        int32_t window_bins, float threshold, int32_t* bin_start,
                                        float* confidence, int32_t* flag, int32_t* zoom_list,
                                        int32_t* fallback_list, int32_t* counts, int32_t* done,
-                                       const PulseExpArgs& pe, hipStream_t s);
+                                       int32_t* fb_slot, const PulseExpArgs& pe, hipStream_t s);
 hipError_t launch_window_peak(const float* spectra, int32_t n_gates, int32_t window_bins,
                               int32_t fine_len, const int32_t* bin_start, const int32_t* list,
                               const int32_t* count, int32_t* peak_bin, float* peak_power,

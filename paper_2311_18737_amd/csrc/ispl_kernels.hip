@@ -29,6 +29,8 @@
 
 #include <hip/hip_runtime.h>
 #include <limits.h>
+
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -360,10 +362,47 @@ __device__ __forceinline__ int work_id(const FusedArgs& a) {
   return a.gate_list ? static_cast<int>(blockIdx.x) : xcd_block_id();
 }
 
-// Output row of gate g (chunk c when the pulses are split).
-__device__ __forceinline__ float* out_row(const FusedArgs& a, int g, int c) {
-  return a.out + (a.chunks == 1 ? static_cast<int64_t>(g) * a.n_fft
-                                : (static_cast<int64_t>(c) * a.n_gates + g) * a.n_fft);
+// The work item of this workgroup: gate g (-1: nothing to do), bin group zg,
+// pulse chunk c of `chunks`; `slot` is the gate's position in the list and
+// `rows` the rows of one chunk's partials.  Work items are numbered
+// (slot, zg, c) with c fastest.  With adaptive chunking the chunk count comes
+// from the device-side list length (the same rule the host sized the grid
+// with), and workgroups past the work of that length return at once.
+struct WorkItem {
+  int g, zg, c, chunks, slot, rows;
+};
+
+__device__ __forceinline__ WorkItem work_item(const FusedArgs& a, int zgroups) {
+  WorkItem w;
+  int bid = work_id(a);
+  if (a.adapt_target > 0) {
+    const int k = min(max(*a.gate_count, 0), a.n_gates);
+    w.chunks = adaptive_chunks(k, zgroups, a.adapt_target, a.adapt_max_chunks, a.adapt_rows);
+    w.rows = k;
+    if (bid >= k * zgroups * w.chunks) {
+      w.g = -1;
+      return w;
+    }
+  } else {
+    w.chunks = a.chunks;
+    w.rows = a.n_gates;
+  }
+  w.c = bid % w.chunks;
+  bid /= w.chunks;
+  w.zg = bid % zgroups;
+  w.slot = bid / zgroups;
+  w.g = slot_gate(a, w.slot);
+  return w;
+}
+
+// Output row of a work item: the gate's row of `out` with one chunk, else
+// the chunk's partial row (chunk-major [C][G][N] in `out`, or [C][k][N] by
+// list slot in adapt_partial).
+__device__ __forceinline__ float* out_row(const FusedArgs& a, const WorkItem& w) {
+  if (w.chunks == 1) return a.out + static_cast<int64_t>(w.g) * a.n_fft;
+  if (a.adapt_target > 0)
+    return a.adapt_partial + (static_cast<int64_t>(w.c) * w.rows + w.slot) * a.n_fft;
+  return a.out + (static_cast<int64_t>(w.c) * a.n_gates + w.g) * a.n_fft;
 }
 
 // Code lengths L <= 1024: one wave per bin class k1 (sub-transform length 1024).
@@ -393,18 +432,15 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int R = 1 << a.log2_r;
   const int zgroups = R / RW;
-  int bid = work_id(a);
-  const int c = bid % a.chunks;
-  bid /= a.chunks;
-  const int zg = bid % zgroups;
-  const int g = slot_gate(a, bid / zgroups);
+  const WorkItem w = work_item(a, zgroups);
+  const int g = w.g, zg = w.zg, c = w.c;
   if (g < 0) return;  // uniform over the workgroup, before any barrier
   const int k1 = zg * RW + wave;
   const int L = a.code_len;
   const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
 
-  const int p0 = static_cast<int>((static_cast<int64_t>(c) * a.n_pulses) / a.chunks);
-  const int p1 = static_cast<int>((static_cast<int64_t>(c + 1) * a.n_pulses) / a.chunks);
+  const int p0 = static_cast<int>((static_cast<int64_t>(c) * a.n_pulses) / w.chunks);
+  const int p1 = static_cast<int>((static_cast<int64_t>(c + 1) * a.n_pulses) / w.chunks);
 
   WaveTwiddles wt;
   load_wave_twiddles(wt, tw, a.n_fft, k1, lane);
@@ -493,8 +529,8 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
     for (int kd = 0; kd < 4; ++kd)
       st[(ka + 16 * (4 * row + t) + 256 * kd) * RW + wave] = acc[4 * t + kd];
   __syncthreads();
-  float* out = out_row(a, g, c);
-  const bool add = (a.chunks == 1) && a.accumulate;
+  float* out = out_row(a, w);
+  const bool add = (w.chunks == 1) && a.accumulate;
   for (int e = tid; e < RW * SUB; e += NT) {
     float* dst = out + zg * RW + e % RW + R * (e / RW);
     *dst = add ? (*dst + st[e]) : st[e];
@@ -540,18 +576,15 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int R = 1 << a.log2_r;  // N / 16384
-  int bid = work_id(a);
-  const int c = bid % a.chunks;
-  bid /= a.chunks;
-  const int k1 = bid % R;
-  const int g = slot_gate(a, bid / R);
+  const WorkItem w = work_item(a, R);
+  const int g = w.g, k1 = w.zg, c = w.c;
   if (g < 0) return;  // uniform over the workgroup, before any barrier
   const int N = a.n_fft;
   const int L = a.code_len;
   const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
 
-  const int p0 = static_cast<int>((static_cast<int64_t>(c) * a.n_pulses) / a.chunks);
-  const int p1 = static_cast<int>((static_cast<int64_t>(c + 1) * a.n_pulses) / a.chunks);
+  const int p0 = static_cast<int>((static_cast<int64_t>(c) * a.n_pulses) / w.chunks);
+  const int p1 = static_cast<int>((static_cast<int64_t>(c + 1) * a.n_pulses) / w.chunks);
 
   float2 xpre[16];  // W_N^{1024 k1 j}: same for every thread
 #pragma unroll
@@ -633,8 +666,8 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
     for (int kd = 0; kd < 4; ++kd)
       st[wave + 16 * (ka + 16 * (4 * row + t) + 256 * kd)] = acc[4 * t + kd];
   __syncthreads();
-  float* out = out_row(a, g, c);
-  const bool add = (a.chunks == 1) && a.accumulate;
+  float* out = out_row(a, w);
+  const bool add = (w.chunks == 1) && a.accumulate;
   for (int e = tid; e < 16 * SUB; e += 1024) {
     float* dst = out + k1 + R * e;
     *dst = add ? (*dst + st[e]) : st[e];
@@ -757,10 +790,24 @@ peak_pick(const float* __restrict__ spectra, int32_t n_gates, int32_t n_fft, int
   }
 }
 
+// Workgroups of a fused launch: every (gate, bin group, chunk) work item, or
+// with adaptive chunking the most work items any list length can ask for.
+int64_t fused_blocks(const FusedArgs& a, int zgroups) {
+  if (a.adapt_target <= 0) return static_cast<int64_t>(a.n_gates) * zgroups * a.chunks;
+  auto items = [&](int k) {
+    return static_cast<int64_t>(k) * zgroups *
+           adaptive_chunks(k, zgroups, a.adapt_target, a.adapt_max_chunks, a.adapt_rows);
+  };
+  int64_t most = items(a.n_gates);
+  const int kmax = std::min(a.n_gates, a.adapt_target / zgroups + 1);
+  for (int k = 1; k <= kmax; ++k) most = std::max(most, items(k));
+  return most;
+}
+
 template <int RW, int ST>
 hipError_t launch_fused_t(const FusedArgs& a, hipStream_t stream) {
   const int zgroups = (1 << a.log2_r) / RW;
-  const int64_t blocks = static_cast<int64_t>(a.n_gates) * zgroups * a.chunks;
+  const int64_t blocks = fused_blocks(a, zgroups);
   // one-wave workgroups prefetch when the launch has at most two waves per SIMD
   constexpr int64_t kPrefetchMaxWaves = 2 * 4 * 256;
   if constexpr (RW == 1) {
@@ -788,7 +835,7 @@ hipError_t launch_fused_t(const FusedArgs& a, hipStream_t stream) {
 
 template <int ST>
 hipError_t launch_fused_long_t(const FusedArgs& a, hipStream_t stream) {
-  const int64_t blocks = static_cast<int64_t>(a.n_gates) * (1 << a.log2_r) * a.chunks;
+  const int64_t blocks = fused_blocks(a, 1 << a.log2_r);
   if (a.code_len <= 2 * SUB)
     hipLaunchKernelGGL((fused_spectra_long<ST, true>), dim3(static_cast<unsigned>(blocks)),
                        dim3(1024), 0, stream, a);

@@ -9,14 +9,20 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cassert>
+#include <chrono>
+#include <condition_variable>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ispl_internal.h"
@@ -60,7 +66,67 @@ struct MGraph {
 struct MExec {
   std::vector<std::function<void()>> ops;
   bool alive = true;
+  int inflight = 0;  // launches whose completion bookkeeping has not run yet
 };
+
+// Completion of graph launches, as a runtime's own completion thread does it:
+// a launch's operations run at once (stream order is kept by running every
+// operation on the calling thread), its event markers are signalled at once,
+// but the release of the launch's references to the executable graph happens
+// later, on this thread.  Only hipDeviceSynchronize waits for those releases;
+// stream and event synchronisation do not.  Destroying an executable while a
+// release is pending is an error of the caller (reported at the destroy), and
+// the late release then touches freed memory (reported by AddressSanitizer).
+namespace completion {
+std::mutex mu;
+std::condition_variable cv, drained;
+std::deque<std::pair<MExec*, std::chrono::steady_clock::time_point>> pending;
+std::thread worker;
+bool stop = false;
+
+void run() {
+  std::unique_lock<std::mutex> lock(mu);
+  for (;;) {
+    cv.wait(lock, [] { return stop || !pending.empty(); });
+    if (pending.empty()) return;
+    const auto due = pending.front().second;
+    if (cv.wait_until(lock, due, [] { return stop && pending.empty(); })) return;
+    if (std::chrono::steady_clock::now() < due) continue;
+    MExec* e = pending.front().first;
+    pending.pop_front();
+    e->inflight -= 1;  // the runtime's release of its reference
+    if (pending.empty()) drained.notify_all();
+  }
+}
+
+void start() {
+  if (!worker.joinable()) worker = std::thread(run);
+}
+
+void launched(MExec* e) {
+  std::lock_guard<std::mutex> lock(mu);
+  start();
+  e->inflight += 1;
+  pending.emplace_back(e, std::chrono::steady_clock::now() + std::chrono::milliseconds(20));
+  cv.notify_all();
+}
+
+void drain() {
+  std::unique_lock<std::mutex> lock(mu);
+  drained.wait(lock, [] { return pending.empty(); });
+}
+
+struct Joiner {
+  ~Joiner() {
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      stop = true;
+    }
+    cv.notify_all();
+    if (worker.joinable()) worker.join();
+  }
+} joiner;
+}  // namespace completion
 struct MEvent {
   int capture = 0;  // capture id it was recorded in (0: eager)
   MStream* from = nullptr;
@@ -115,7 +181,10 @@ hipError_t hipGetDevicePropertiesR0600(hipDeviceProp_tR0600* p, int) {
 static int g_dev = 0;
 hipError_t hipGetDevice(int* d) { *d = g_dev; return hipSuccess; }
 hipError_t hipSetDevice(int d) { g_dev = d; return hipSuccess; }
-hipError_t hipDeviceSynchronize() { return hipSuccess; }
+hipError_t hipDeviceSynchronize() {
+  completion::drain();
+  return hipSuccess;
+}
 hipError_t hipGetLastError() { return hipSuccess; }
 const char* hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "mock error"; }
 
@@ -282,6 +351,14 @@ hipError_t hipGraphDestroy(hipGraph_t g) {
 hipError_t hipGraphExecDestroy(hipGraphExec_t x) {
   MExec* e = reinterpret_cast<MExec*>(x);
   if (!g_execs.erase(e)) { fprintf(stderr, "MOCK: destroy unknown exec\n"); ++g_errors; return hipErrorInvalidValue; }
+  {
+    std::lock_guard<std::mutex> lock(completion::mu);
+    if (e->inflight > 0) {
+      fprintf(stderr, "MOCK: executable graph destroyed while %d launch(es) of it are still "
+              "being completed by the runtime\n", e->inflight);
+      ++g_errors;
+    }
+  }
   delete e;
   return hipSuccess;
 }
@@ -290,6 +367,7 @@ hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s) {
   if (!g_execs.count(e)) { fprintf(stderr, "MOCK: launch unknown exec\n"); ++g_errors; return hipErrorInvalidValue; }
   if (S(s)->capture) { fprintf(stderr, "MOCK: graph launch into a capture\n"); ++g_errors; }
   for (auto& op : e->ops) op();
+  completion::launched(e);
   return hipSuccess;
 }
 
@@ -370,6 +448,19 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t st) {
     }
     if (c.chunks < 1) mock_fail("fused: no pulse chunk");
     check_range(c.twiddle, size_t(c.n_fft) * 8, "fused twiddle");
+    if (c.adapt_target > 0) {  // chunk count from the list length, rows by list slot
+      if (!c.gate_list) mock_fail("fused: adaptive chunking without a list");
+      const int zg = c.sub_len == SUB ? R / c.waves_per_block : R;
+      const int k = static_cast<int>(gs.size());
+      const int C = adaptive_chunks(k, zg, c.adapt_target, c.adapt_max_chunks, c.adapt_rows);
+      if (C == 1) {
+        check_rows(c.out, c.n_fft, gs, "fused out");
+      } else {
+        if (C * k > c.adapt_rows) mock_fail("fused: adaptive partial rows overflow");
+        check_range(c.adapt_partial, size_t(C) * k * c.n_fft * 4, "fused adaptive partial");
+      }
+      return;
+    }
     for (int k = 0; k < c.chunks; ++k)
       check_rows(c.out + int64_t(k) * c.n_gates * c.n_fft, c.n_fft, gs, "fused out");
   });
@@ -550,10 +641,16 @@ hipError_t launch_peak(const float* spectra, int32_t n_gates, int32_t n_fft, int
 
 // The window decision's outputs, written the way the kernel writes them (a
 // fixed pattern of zoomed gates stands in for the network's confidence).
+// The decision pattern cycles over calls: one gate in five falls back, then a
+// single gate, then none (the adaptive fallback chunking sees many, one and
+// no fallback gates).
+static int g_select_calls = 0;
+
 static void emulate_select(const float* logits, int32_t G, int32_t fine_len, int32_t K,
                            int32_t* bin_start, float* confidence, int32_t* flag,
                            int32_t* zoom_list, int32_t* fallback_list, int32_t* counts,
-                           int32_t* done) {
+                           int32_t* done, int32_t* fb_slot = nullptr) {
+  const int pattern = g_select_calls++ % 3;
   if (G < 1) mock_fail("select launch with an empty grid");
   if (fine_len < T_NET || fine_len % T_NET != 0 || K < 1 || K > fine_len)
     mock_fail("select window geometry");
@@ -566,12 +663,14 @@ static void emulate_select(const float* logits, int32_t G, int32_t fine_len, int
   ok = check_range(done, 4, "select done") && ok;
   if (!ok) return;
   if (*done != 0) mock_fail("select: completion counter not zero at the start of a call");
+  if (fb_slot && !check_range(fb_slot, size_t(G) * 4, "select fallback slots")) return;
   int nz = 0;
   for (int g = 0; g < G; ++g) {
-    const bool z = (g * 7 + 3) % 5 != 0;
+    const bool z = pattern == 0 ? (g * 7 + 3) % 5 != 0 : pattern == 1 ? g != G / 2 : true;
     flag[g] = z ? 1 : 0;
     bin_start[g] = static_cast<int32_t>((int64_t(g) * 997) % fine_len);
     if (confidence) confidence[g] = z ? 0.95f : 0.5f;
+    if (fb_slot) fb_slot[g] = z ? -1 : g - nz;
     if (z)
       zoom_list[nz++] = g;
     else
@@ -598,11 +697,11 @@ hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int
                                        int32_t window_bins, float, int32_t* bin_start,
                                        float* confidence, int32_t* flag, int32_t* zoom_list,
                                        int32_t* fallback_list, int32_t* counts, int32_t* done,
-                                       const PulseExpArgs& pe, hipStream_t st) {
+                                       int32_t* fb_slot, const PulseExpArgs& pe, hipStream_t st) {
   PulseExpArgs e = pe;
   run_on(st, [=] {
     emulate_select(logits, n_gates, fine_len, window_bins, bin_start, confidence, flag, zoom_list,
-                   fallback_list, counts, done);
+                   fallback_list, counts, done, fb_slot);
     if (e.n_pulses < 0) mock_fail("negative pulse count");
     check_pulse_exponents(e.samples, e.sample_type, e.tx, e.stride, e.lo, e.hi, e.code_len,
                           e.tx_per_pulse, e.n_pulses, e.exps);
@@ -611,23 +710,36 @@ hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int
 }
 
 hipError_t launch_split_peaks(float* window_spectra, const float* window_partial,
-                              int32_t zoom_chunks, float* full_spectra, const float* full_partial,
-                              int32_t fine_chunks, const int32_t* flag, const int32_t* bin_start,
-                              int32_t n_gates, int32_t window_bins, int32_t fine_len,
-                              int32_t* peak_bin, float* peak_power, hipStream_t st) {
+                              int32_t zoom_chunks, float* full_spectra, const FallbackChunks& f,
+                              const int32_t* flag, const int32_t* bin_start, int32_t n_gates,
+                              int32_t window_bins, int32_t fine_len, int32_t* peak_bin,
+                              float* peak_power, hipStream_t st) {
+  const FallbackChunks fb = f;
   run_on(st, [=] {
     if (n_gates < 1) mock_fail("split peaks with an empty grid");
     if (!check_range(flag, size_t(n_gates) * 4, "split flag")) return;
+    if (!check_range(fb.counts, 8, "split counts")) return;
+    const int k = std::min(std::max(fb.counts[1], 0), n_gates);
+    const int fchunks = adaptive_chunks(k, fb.zgroups, fb.target, fb.max_chunks, fb.rows);
+    if (fchunks > 1 && fchunks * k > fb.rows) mock_fail("split: fallback partial rows overflow");
     for (int g = 0; g < n_gates; ++g) {
       const bool z = flag[g] != 0;
       const int64_t len = z ? window_bins : fine_len;
-      const int chunks = z ? zoom_chunks : fine_chunks;
-      const float* part = z ? window_partial : full_partial;
       check_range((z ? window_spectra : full_spectra) + g * len, size_t(len) * 4, "split row");
-      if (chunks > 1)
-        for (int k = 0; k < chunks; ++k)
-          check_range(part + (int64_t(k) * n_gates + g) * len, size_t(len) * 4, "split partial");
-      if (z) check_range(bin_start + g, 4, "split bin_start");
+      if (z) {
+        if (zoom_chunks > 1)
+          for (int c = 0; c < zoom_chunks; ++c)
+            check_range(window_partial + (int64_t(c) * n_gates + g) * len, size_t(len) * 4,
+                        "split zoom partial");
+        check_range(bin_start + g, 4, "split bin_start");
+      } else if (fchunks > 1) {
+        if (!check_range(fb.slot + g, 4, "split fallback slot")) continue;
+        const int slot = fb.slot[g];
+        if (slot < 0 || slot >= k) mock_fail("split: fallback slot outside the list");
+        for (int c = 0; c < fchunks; ++c)
+          check_range(fb.partial + (int64_t(c) * k + slot) * len, size_t(len) * 4,
+                      "split fallback partial");
+      }
     }
     check_range(peak_bin, size_t(n_gates) * 4, "split peak bin");
     if (peak_power) check_range(peak_power, size_t(n_gates) * 4, "split peak power");

@@ -99,9 +99,6 @@ def test_batch_equals_each_mode_bit_for_bit(ispl, st):
     b.close()
 
 
-@pytest.mark.skip(reason="the library's batch autotuner is switched off: a process running it "
-                         "(this test) ended in a host-side segmentation fault whose cause is not "
-                         "found yet; it stays off the GPU until it is")
 def test_autotuner(ispl):
     geo, data = make(MODES, seed=5)
     inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
@@ -119,13 +116,25 @@ def test_autotuner(ispl):
     b.close()
 
 
-def test_autotuner_reports_switched_off(ispl):
+def test_autotuner_rejects_bad_trials_and_recaptures(ispl):
     geo, data = make(MODES[:2], seed=6)
     inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
     b = ispl.Batch(geo)
     with pytest.raises(ispl.IsplError) as err:
-        b.tune(inputs, trials=2)
-    assert err.value.status == ispl.ISPL_ERR_UNSUPPORTED
+        b.tune(inputs, trials=0)
+    assert err.value.status == ispl.ISPL_ERR_INVALID_ARG
+    # re-captures straight after graph launches, more than the object keeps
+    # replaced graphs, then a tune and a replay on the same object
+    outs = b.integrate(inputs)
+    for i in range(18):
+        b.integrate(inputs, outs, accumulate=bool(i % 2))
+    plan, ms = b.tune(inputs, trials=1)
+    b.integrate(inputs, outs)
+    torch.cuda.synchronize()
+    ref = per_mode(ispl, geo, data, "c64")
+    for o, r in zip(outs, ref):
+        scale = torch.maximum(r, r.mean(dim=1, keepdim=True))
+        assert float(((o - r).abs() / torch.clamp(scale, min=1e-30)).max()) <= 2e-6
     b.close()
 
 
