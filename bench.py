@@ -34,9 +34,16 @@ def log(msg):
 
 
 def flops_per_spectrum(n_fft: int, code_len: int) -> float:
-    """Algorithmic FP32 work of one pulse-gate spectrum: the conventional
-    5 N log2 N of a complex FFT, 4 N for |X|^2 and its accumulation, 6 L for
-    the complex decode multiply."""
+    """Algorithmic work of one pulse-gate spectrum, the unit of the roofline:
+    the conventional 5 N log2 N of a complex FFT, 2 N for the power and its
+    accumulation, 2 L for the decode."""
+    return 5.0 * n_fft * math.log2(n_fft) + 2.0 * n_fft + 2.0 * code_len
+
+
+def flops_per_spectrum_full_count(n_fft: int, code_len: int) -> float:
+    """The same with every real operation counted: 4 N for |X|^2 and its
+    accumulation (two products, two sums), 6 L for the complex decode multiply.
+    Reported beside the roofline, never as its fraction."""
     return 5.0 * n_fft * math.log2(n_fft) + 4.0 * n_fft + 6.0 * code_len
 
 
@@ -67,31 +74,59 @@ def measured_traffic():
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(d, cfg, budget_s: float):
-    """The FP64 oracle as it stands, timed on the host on a bounded sample:
-    whole gates (all pulses each) until the time budget is spent."""
+_CPU_JOB = None  # (dataset, config) of the oracle baseline, inherited by forked workers
+
+
+def _oracle_gates(gates):
     from oracle import integrate_spectra
 
-    gates = []
-    t0 = time.perf_counter()
-    g = 0
-    while g < cfg.n_gates:
-        integrate_spectra(d.samples, d.tx, n_gates=cfg.n_gates, gate_step=cfg.gate_step,
-                          first_gate=cfg.first_gate, fft_len=cfg.fft_len, tx_per_pulse=True,
-                          gates=[g])
-        gates.append(g)
-        g += max(1, cfg.n_gates // 97)  # spread the sample over the range
-        if time.perf_counter() - t0 >= budget_s:
-            break
-    dt = time.perf_counter() - t0
-    spectra = len(gates) * cfg.n_pulses
+    d, cfg = _CPU_JOB
+    integrate_spectra(d.samples, d.tx, n_gates=cfg.n_gates, gate_step=cfg.gate_step,
+                      first_gate=cfg.first_gate, fft_len=cfg.fft_len, tx_per_pulse=True,
+                      gates=list(gates))
+    return len(gates)
+
+
+def cpu_baseline(d, cfg, budget_s: float):
+    """The FP64 oracle as it stands, timed on the host cores on a bounded
+    sample: whole gates (all pulses each), spread over the range, one oracle
+    call per worker process (forked before the GPU is touched).  Worker count:
+    the cores this process may run on, at most 16 (one GPU's share of a box)."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    global _CPU_JOB
+    _CPU_JOB = (d, cfg)
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    # one gate, then two: the difference is one gate's work, the rest the
+    # oracle's conversion of the rows, paid once per call
+    t = []
+    for n in (1, 2):
+        t0 = time.perf_counter()
+        _oracle_gates(range(n))
+        t.append(time.perf_counter() - t0)
+    per_gate = max(t[1] - t[0], 1e-3)
+    fixed = max(t[0] - per_gate, 0.0)
+    per_worker = max(1, int((budget_s - fixed) / per_gate))
+    n_gates = min(cfg.n_gates, cores * per_worker)
+    gates = np.unique(np.linspace(0, cfg.n_gates - 1, n_gates).astype(np.int64))
+    groups = [gates[i::cores] for i in range(cores) if len(gates[i::cores])]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(len(groups)) as pool:
+        t0 = time.perf_counter()
+        done = sum(pool.map(_oracle_gates, groups, chunksize=1))
+        dt = time.perf_counter() - t0
+    _CPU_JOB = None
+    spectra = done * cfg.n_pulses
     return {
         "value": spectra / dt,
         "unit": "spectra/s",
-        "cores": 1,
+        "cores": len(groups),
         "kind": "oracle",
-        "sample": f"{len(gates)} gates x {cfg.n_pulses} pulses of the workload "
-                  f"({spectra} pulse-gate spectra, {dt:.1f} s, float64 numpy, 1 thread)",
+        "sample": f"{done} of {cfg.n_gates} gates x {cfg.n_pulses} pulses of the workload "
+                  f"({spectra} pulse-gate spectra, {dt:.1f} s wall on {len(groups)} worker "
+                  f"processes, one oracle call each; float64 numpy)",
     }
 
 
@@ -156,6 +191,58 @@ def paper_workload(steps: int, seed: int, dev):
                                       "timing; copy of the gate span overlapped with "
                                       "integration (streaming ingest)"),
     }
+
+
+def small_workload(steps: int, seed: int, dev):
+    """The small configuration (100 pulses x 64 gates, code length 256,
+    N = 1024, complex64): integration + peak pick per step, HIP events on the
+    launch stream.  At this size a step is bound by launch latency, not by
+    the transform."""
+    import numpy as np
+    import torch
+
+    import paper_2311_18737_amd as ispl
+    from synth import CONFIGS, make_dataset
+
+    cfg = CONFIGS["small"]
+    d = make_dataset(cfg, seed)
+    xs = torch.from_numpy(d.samples).to(dev)
+    xt = torch.from_numpy(d.tx).to(dev)
+    geo = dict(code_len=cfg.code_len, fft_len=cfg.fft_len, n_gates=cfg.n_gates,
+               gate_step=cfg.gate_step, first_gate=cfg.first_gate,
+               pulse_stride=cfg.pulse_stride, sample_type=cfg.sample_type)
+    ctx = ispl.Context(max_pulses=cfg.n_pulses, device=0, **geo)
+    S = torch.empty((cfg.n_gates, cfg.fft_len), dtype=torch.float32, device=dev)
+    bins = torch.empty(cfg.n_gates, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        ctx.integrate_spectra(xs, xt, out=S, stream=stream)
+        ctx.find_plasma_line(S, out_bins=bins, want_power=False, stream=stream)
+
+    def noalloc_step():
+        ispl.integrate_spectra_noalloc(xs, xt, S, max_pulses=cfg.n_pulses, stream=stream, **geo)
+        ctx.find_plasma_line(S, out_bins=bins, want_power=False, stream=stream)
+
+    out = {"workload": "small: 100 pulses x 64 gates, code length 256, FFT N=1024, complex64",
+           "plan": ispl.plan(cfg.n_pulses, max_pulses=cfg.n_pulses, **geo)}
+    for name, fn in (("context", step), ("noalloc", noalloc_step)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        for a, b in ev:
+            a.record(stream)
+            fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+        out[name] = {"ms_per_step": ms,
+                     "spectra_per_s": cfg.n_pulses * cfg.n_gates / (ms / 1e3)}
+    ctx.close()
+    log(f"small workload: {out}")
+    return out
 
 
 def zoom_study(steps: int, seed: int, dev):
@@ -285,8 +372,8 @@ def streaming_time(d, cfg, dev, slot_pulses: int, reps: int = 3):
 def batch_study(steps: int, seed: int, dev):
     """Uneven batch: four experiments (code lengths 128/480/1000/2000, FFT
     lengths 4096/8192/16384/32768, 200/600/1000/2000 gates, 500 pulses each)
-    in one launch of a HIP graph (the autotuner's plan where the library has
-    it, else the automatic plan), against the same four experiments run one
+    in one launch of a HIP graph (the autotuner's plan; the automatic plan's
+    graphs are timed beside it), against the same four experiments run one
     after another through ispl_integrate_spectra."""
     import numpy as np
     import torch
@@ -328,21 +415,15 @@ def batch_study(steps: int, seed: int, dev):
     t_seq = timed(sequential)
     b = ispl.Batch(geo)
     outs = [torch.empty_like(o) for o in seq_out]
+    # the automatic plan's graph in both shapes (a parallel branch per
+    # experiment, or one serial branch), then the autotuner's plan
     graph_ms = {}
-    try:
-        plan, tuned_ms = b.tune(data, outs, trials=3)
-        log(f"batch: tuned plan {plan} ({tuned_ms:.3f} ms)")
-    except ispl.IsplError as err:  # autotuner switched off in this build
-        # automatic tile shapes; of the two graph shapes (a parallel branch per
-        # experiment, or one serial branch) keep the faster
-        tuned_ms = None
-        for serial in (False, True):
-            b.set_plan(serial=serial)
-            graph_ms["serial" if serial else "parallel"] = timed(
-                lambda: b.integrate(data, outs, use_graph=True, stream=stream))
-        b.set_plan(serial=graph_ms["serial"] < graph_ms["parallel"])
-        plan = b.plan()
-        log(f"batch: automatic plan {plan}, graph shapes {graph_ms} ({err})")
+    for serial in (False, True):
+        b.set_plan(serial=serial)
+        graph_ms["auto_serial" if serial else "auto_parallel"] = timed(
+            lambda: b.integrate(data, outs, use_graph=True, stream=stream))
+    plan, tuned_ms = b.tune(data, outs, trials=3)
+    log(f"batch: tuned plan {plan} ({tuned_ms:.3f} ms eager), automatic plan graphs {graph_ms}")
     t_batch = timed(lambda: b.integrate(data, outs, use_graph=True, stream=stream))
     torch.cuda.synchronize()
     worst = 0.0
@@ -356,7 +437,7 @@ def batch_study(steps: int, seed: int, dev):
            "batch_ms": t_batch, "sequential_ms": t_seq, "speedup_vs_sequential": t_seq / t_batch,
            "spectra_per_s": units / (t_batch / 1e3),
            "nominal_TFLOPs": flops / (t_batch / 1e3) / 1e12,
-           "plan": plan, "tuned_ms": tuned_ms, "graph_shape_ms": graph_ms or None,
+           "plan": plan, "tuned_ms": tuned_ms, "auto_plan_graph_ms": graph_ms,
            "max_rel_diff_vs_sequential": worst}
     log(f"batch: {out}")
     b.close()
@@ -365,7 +446,7 @@ def batch_study(steps: int, seed: int, dev):
     return out
 
 
-def learned_zoom_study(steps: int, seed: int, dev, shapes=("c1", "large")):
+def learned_zoom_study(steps: int, seed: int, dev, shapes=("c1", "large", "large_fallback")):
     """Learned zoom against the plain path on the same held-out data.
 
     Plain: ispl_integrate_spectra at N = 16384 for every gate, then
@@ -405,7 +486,11 @@ def learned_zoom_study(steps: int, seed: int, dev, shapes=("c1", "large")):
     variants = {"c1": (base, "learned-zoom workload on the small shape: 100 pulses x 64 gates, "
                              "code length 256, lines U(1,15) MHz, SNR U(-25,-5) dB per gate"),
                 "large": (base.replace(n_pulses=1000, n_gates=1000),
-                          "same content at 1000 pulses x 1000 gates")}
+                          "same content at 1000 pulses x 1000 gates"),
+                "large_fallback": (base.replace(n_pulses=1000, n_gates=1000, silent_every=50),
+                                   "same content at 1000 pulses x 1000 gates, every 50th range "
+                                   "cell without a line (2 % noise-only gates, which the "
+                                   "network should send to the full-FFT fallback)")}
     out = {}
     for key in shapes:
         cfg, text = variants[key]
@@ -432,11 +517,13 @@ def learned_zoom_study(steps: int, seed: int, dev, shapes=("c1", "large")):
         t_plain = timed(plain)
         t_learned = timed(learned)
         torch.cuda.synchronize()
-        n_zoom = int(lz.view()["counts"][0].item())
+        counts = lz.view()["counts"].cpu().numpy()
+        n_zoom = int(counts[0])
         e = np.abs(lb.cpu().numpy().astype(np.int64) - pb.cpu().numpy().astype(np.int64))
         e = np.minimum(e, cfg.fft_len - e)
         out[key] = {"workload": text, "plain_ms": t_plain, "learned_ms": t_learned,
                     "speedup": t_plain / t_learned,
+                    "zoomed_gates": n_zoom, "fallback_gates": int(counts[1]),
                     "zoomed_fraction": n_zoom / cfg.n_gates,
                     "within_1_bin_of_plain": float(np.mean(e <= 1))}
         # the same two paths replayed from HIP graphs (launch overhead removed);
@@ -490,6 +577,8 @@ def main():
                     help="timed runs from pinned host memory (streaming ingest; 0 = skip)")
     ap.add_argument("--lzoom-steps", type=int, default=20,
                     help="timed runs of the learned-zoom study (0 = skip)")
+    ap.add_argument("--small-steps", type=int, default=50,
+                    help="timed steps of the small configuration (0 = skip)")
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -508,6 +597,12 @@ def main():
     cfg = CONFIGS[WORKLOAD]
     log(f"drawing {cfg.n_pulses} pulses x {cfg.n_gates} gates (seed {args.seed})")
     d = make_dataset(cfg, args.seed, progress=lambda p, n: log(f"  {p}/{n} pulses"))
+    cpu = None
+    if args.cpu_budget > 0:
+        # the oracle's worker processes are forked before anything touches the GPU
+        log(f"timing the oracle on the host cores ({args.cpu_budget:.0f} s budget)")
+        cpu = cpu_baseline(d, cfg, args.cpu_budget)
+        log(f"oracle baseline: {cpu}")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     xs = torch.from_numpy(d.samples).to(dev)
@@ -571,6 +666,7 @@ def main():
     alg_bytes = algorithmic_bytes(cfg, bps)
     traffic = measured_traffic()
 
+    small = small_workload(args.small_steps, args.seed, dev) if args.small_steps > 0 else None
     paper = paper_workload(args.paper_steps, args.seed, dev) if args.paper_steps > 0 else None
     zoom = zoom_study(args.zoom_steps, args.seed, dev) if args.zoom_steps > 0 else None
     lzoom = (learned_zoom_study(args.lzoom_steps, args.seed, dev)
@@ -583,11 +679,6 @@ def main():
         streaming = streaming_time(d, cfg, dev, slot_pulses=100, reps=args.stream_reps)
         streaming["device_resident_ms"] = ms_per_step
         log(f"streaming ingest: {streaming}")
-
-    cpu = None
-    if args.cpu_budget > 0:
-        log(f"timing the oracle on the host ({args.cpu_budget:.0f} s budget)")
-        cpu = cpu_baseline(d, cfg, args.cpu_budget)
 
     value = units / (ms_per_step / 1e3)
     out = {
@@ -618,6 +709,11 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved_tflops / PEAK_FP32_TFLOPS,
             "traffic": traffic,
+            "flop_per_unit": flops_per_spectrum(cfg.fft_len, cfg.code_len),
+            "units_per_launch": units,
+            "kernel_ms_mean_hip_events": t_kernel * 1e3,
+            "full_count_achieved": units * flops_per_spectrum_full_count(cfg.fft_len, cfg.code_len)
+                                   / t_kernel / 1e12,
         },
         "hbm": {
             "algorithmic_bytes": alg_bytes,
@@ -628,6 +724,7 @@ def main():
                       "integrate_min": float(np.min(integ_ms)),
                       "peak_pick_mean": float(np.mean(peak_ms))},
         "realtime_factor": (cfg.n_pulses * 10e-3) / (ms_per_step / 1e3),
+        "small_workload": small,
         "paper_workload": paper,
         "zoom": zoom,
         "learned_zoom": lzoom,

@@ -16,7 +16,8 @@ plasma line, so for pulse p and range r with start sample t_r = g0 + r*s:
     f_{p,r}  = f_line(r) + delta_{p,r},  delta ~ N(0, (w / 2.3548)**2)
 
 (with ``echo_stride`` q > 1 only every q-th range cell echoes, which keeps
-drawing workloads with long codes and thousands of gates cheap).  With
+drawing workloads with long codes and thousands of gates cheap; with
+``silent_every`` q > 0 every q-th range cell carries no line).  With
 ``snr_db_range`` set, rho is drawn per range cell, uniformly in dB.
 
 f_line(r) follows an alpha-Chapman electron-density layer: the plasma
@@ -79,6 +80,9 @@ class EchoConfig:
     tx_per_pulse: bool = True
     stride_align: int = 64
     echo_stride: int = 1  # only ranges r with r % echo_stride == 0 carry a line
+    # q > 0: ranges r with r % q == q // 2 carry no line at all (noise only), a
+    # share 1/q of gates where no window of the spectrum holds a line
+    silent_every: int = 0
 
     def replace(self, **kw) -> "EchoConfig":
         return dataclasses.replace(self, **kw)
@@ -233,7 +237,8 @@ def _cached(cfg: EchoConfig, seed: int, progress, cache_dir: str) -> Dataset:
         return Dataset(cfg=cfg, seed=seed, samples=np.load(files["samples"]),
                        tx=np.load(files["tx"]), f_line_hz=np.load(files["fline"]),
                        f_peak_hz=float(sc[0]), rho=float(sc[1]),
-                       rho_gate=rg if cfg.snr_db_range is not None else None)
+                       rho_gate=rg if (cfg.snr_db_range is not None or cfg.silent_every > 0)
+                       else None)
     d = _draw(cfg, seed, progress)
     rg = d.rho_gate if d.rho_gate is not None else np.full(cfg.n_gates, d.rho)
     for k, arr in (("samples", d.samples), ("tx", d.tx), ("fline", d.f_line_hz),
@@ -268,6 +273,13 @@ def _draw(cfg: EchoConfig, seed: int, progress) -> Dataset:
         rho = float(rho_gate.mean())
         amp = np.sqrt(rho_gate / 2.0)
 
+    silent = None
+    if cfg.silent_every > 0:
+        silent = np.arange(G) % cfg.silent_every == cfg.silent_every // 2
+        rho_gate = (np.full(G, rho) if rho_gate is None else rho_gate.copy())
+        rho_gate[silent] = 0.0
+        rho = float(rho_gate.mean())
+
     tx = draw_codes(cfg, seed)
     rng_a = _rng(cfg, seed, _STREAM_AMPS)
     rng_j = _rng(cfg, seed, _STREAM_JITTER)
@@ -287,6 +299,8 @@ def _draw(cfg: EchoConfig, seed: int, progress) -> Dataset:
     for p in range(P):
         c = tx[p if cfg.tx_per_pulse else 0]
         a = (rng_a.standard_normal(G) + 1j * rng_a.standard_normal(G)) * amp
+        if silent is not None:
+            a[silent] = 0.0
         f = f_line + (rng_j.standard_normal(G) * sig_w if sig_w > 0 else 0.0)
         a, f = a[echo_r], np.broadcast_to(f, (G,))[echo_r]
         # phase in cycles, reduced to [0, 1) in float64 before the float32 trig call

@@ -145,3 +145,21 @@ def test_zoom_workload_line_power_follows_the_gate_snr(tmp_path):
     # the cache round-trips the per-gate SNR
     d2 = make_dataset(cfg, 2, cache_dir=str(tmp_path))
     assert np.array_equal(d2.rho_gate, d.rho_gate)
+
+
+def test_silent_ranges_carry_no_line():
+    """silent_every: the silent ranges' amplitudes are zero and nothing else
+    changes.  With every range silent the rows do not depend on the SNR; with
+    every 4th silent the other gates keep the same draws as without."""
+    from synth import CONFIGS, make_dataset
+
+    base = CONFIGS["small"].replace(n_pulses=3, n_gates=8)
+    a = make_dataset(base.replace(silent_every=1, snr_db=-3.0), 1)
+    b = make_dataset(base.replace(silent_every=1, snr_db=-30.0), 1)
+    assert np.array_equal(a.samples, b.samples)
+    assert np.all(a.rho_gate == 0.0)
+    q = make_dataset(base.replace(silent_every=4), 1)
+    silent = np.arange(8) % 4 == 2
+    assert np.all(q.rho_gate[silent] == 0.0) and np.all(q.rho_gate[~silent] > 0.0)
+    full = make_dataset(base, 1)
+    assert np.array_equal(q.tx, full.tx) and not np.array_equal(q.samples, full.samples)
