@@ -28,6 +28,9 @@ struct ispl_ctx {
   int32_t force_rw;     // tuned plan (0: automatic): waves per workgroup, L <= 1024 only
   int32_t force_chunks; // tuned plan (0: automatic): pulse chunks, <= chunks_max
   int32_t min_chunk_pulses;  // fewest pulses per chunk of an automatic plan
+  // codes of L > 2 SUB as sign bits (long-code kernel), max_pulses rows
+  uint16_t* code_bits;  // [max_pulses][CODE_BITS_WORDS]
+  int32_t* code_binary; // [max_pulses]
 };
 
 namespace {
@@ -408,6 +411,20 @@ static ispl_status create_ctx(const ispl_config* cfg, int32_t min_chunk_pulses, 
                   hipGetErrorString(e));
     }
   }
+  if (cfg->code_len > 2 * ispl::SUB) {  // the long-code kernel reads binary codes as sign bits
+    const size_t rows = static_cast<size_t>(cfg->max_pulses);
+    e = hipMalloc(reinterpret_cast<void**>(&ctx->code_bits),
+                  rows * ispl::CODE_BITS_WORDS * sizeof(uint16_t));
+    if (e == hipSuccess)
+      e = hipMalloc(reinterpret_cast<void**>(&ctx->code_binary), rows * sizeof(int32_t));
+    if (e != hipSuccess) {
+      if (ctx->code_bits) (void)hipFree(ctx->code_bits);
+      if (ctx->partial) (void)hipFree(ctx->partial);
+      (void)hipFree(ctx->twiddle);
+      delete ctx;
+      return fail(ISPL_ERR_OUT_OF_MEMORY, "code sign bits: %s", hipGetErrorString(e));
+    }
+  }
   *out = ctx;
   return ok();
 }
@@ -423,6 +440,8 @@ void ispl_destroy(ispl_ctx* ctx) {
     (void)hipDeviceSynchronize();
     if (ctx->partial) (void)hipFree(ctx->partial);
     if (ctx->twiddle) (void)hipFree(ctx->twiddle);
+    if (ctx->code_bits) (void)hipFree(ctx->code_bits);
+    if (ctx->code_binary) (void)hipFree(ctx->code_binary);
   }
   delete ctx;
 }
@@ -543,6 +562,14 @@ static ispl_status integrate_impl(ispl_ctx* ctx, const void* samples, const floa
     a.adapt_target = adapt->target;
     a.adapt_max_chunks = adapt->max_chunks;
     a.adapt_rows = adapt->rows;
+  }
+  if (ctx->code_bits) {  // binary code rows go to the long-code kernel as sign bits
+    const int32_t rows = tx_per_pulse ? n_pulses : 1;
+    e = ispl::launch_pack_code_bits(tx_code, rows, c.code_len, ctx->code_bits, ctx->code_binary,
+                                    s);
+    if (e != hipSuccess) return hip_fail(e, "code bits launch");
+    a.code_bits = ctx->code_bits;
+    a.code_binary = ctx->code_binary;
   }
   e = ispl::launch_fused(a, s);
   if (e != hipSuccess) return hip_fail(e, "fused launch");

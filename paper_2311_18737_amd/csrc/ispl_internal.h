@@ -72,7 +72,22 @@ struct FusedArgs {
   int32_t adapt_target;
   int32_t adapt_max_chunks;
   int32_t adapt_rows;
+  // Optional (long codes, L > 2 SUB): codes as sign bits, written by
+  // launch_pack_code_bits for the same tx; NULL = always read tx.
+  const uint16_t* code_bits;     // [rows][SUB]: bit j of word lg is code[lg + SUB j] == -1
+  const int32_t* code_binary;    // [rows]: 1 when every code of the row is +-1 + 0i
 };
+
+// Words of one code row in the sign-bit form (one per first-pass thread).
+constexpr int CODE_BITS_WORDS = SUB;
+
+// Sign bits of binary (+-1 + 0i) codes, for the long-code kernel: for each of
+// `rows` code rows of length L <= 16 SUB, word lg of bits[row] has bit j set
+// when code[row][lg + SUB j] == -1 (positions past L read as +1), and
+// binary[row] = 1 when every code of the row is exactly +-1 with a zero
+// imaginary part (0 otherwise: the row is then read as complex codes).
+hipError_t launch_pack_code_bits(const float* tx, int32_t rows, int32_t code_len,
+                                 uint16_t* bits, int32_t* binary, hipStream_t stream);
 
 constexpr int MAX_BATCH_MODES = 8;
 

@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <math.h>
 #include <stdint.h>
+#include <utility>
 
 #include "ispl_internal.h"
 
@@ -291,11 +292,17 @@ __device__ __forceinline__ void load_wave_twiddles(WaveTwiddles& w, const float2
 // ka = lane & 15, row = lane >> 4 (F including the bin-class factors).
 // K0: the wave's bin class is 0 (N = 1024), so the pass-1 factors are all 1.
 // F4 (with K0): only v[0..3] carry samples (L <= 256); v[4..15] are not read.
-template <bool K0 = false, bool F4 = false>
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
+// `after_exchange` runs right after this wave has issued the reads of its
+// pass-2 inputs: from then until the next call the exchange buffer is free.
+template <bool K0 = false, bool F4 = false, typename Hook = NoHook>
 __device__ __forceinline__ void wave_fft_accumulate(float2 (&v)[16], float2* xw,
                                                     const WaveTwiddles& w,
                                                     const Dft16Consts& dk, float (&acc)[16],
-                                                    int lane) {
+                                                    int lane, Hook after_exchange = Hook{}) {
   const int ka = lane & 15, row = lane >> 4;
   // pass 1: pre-twiddle and 16-point DFT over the stride-64 samples of a lane
   static_assert(!F4 || K0, "four non-zero inputs only in bin class 0");
@@ -314,6 +321,7 @@ __device__ __forceinline__ void wave_fft_accumulate(float2 (&v)[16], float2* xw,
   const int p2base = ka * XPITCH + row;
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = xw[p2base + 4 * m];
+  after_exchange();
   dft16_pre(v, w.tw2, dk);
 
   // pass 3: the 4-point DFT over r runs across the four 16-lane rows.  For
@@ -543,11 +551,12 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
 // DFT over j (pre-twiddled by W_N^{1024 k1 j}); an all-to-all exchange through
 // LDS then hands wave ka the values U_ka[lg], whose 1024-point transform, with
 // the bin-class factor W_N^{lg (k1 + R ka)}, is bins k1 + R (ka + 16 kb).
-// TWO: codes of at most 2048 samples, so only j = 0, 1 carry samples.  The
-// first pass is then X[k] = y0 + t W_16^k with t = y1 W_N^{1024 k1} (half of
-// the outputs as y0 + t W_16^k, the other half as y0 - t W_16^k), and the two
-// samples and codes of the next pulse are fetched during this pulse's work.
-template <int ST>
+// Codes of at most 2048 samples (fused_spectra_long) carry samples in j = 0, 1
+// only: the first pass is X[k] = y0 + t W_16^k with t = y1 W_N^{1024 k1} (half
+// of the outputs as y0 + t W_16^k, the other half as y0 - t W_16^k), and the
+// two samples and codes of the next pulse are fetched during this pulse's
+// work.  Longer codes take fused_spectra_long_dma.  K0: N = 16384, so the only
+// bin class is k1 = 0 and the first pass has no pre-twiddles.
 __device__ __forceinline__ void two_point_pass(float2 (&v)[16], float2 y0, float2 t,
                                                const Dft16Consts& k) {
   // u_m = t W_16^m for m < 8, W_16^m = exp(-2 pi i m / 16)
@@ -567,7 +576,44 @@ __device__ __forceinline__ void two_point_pass(float2 (&v)[16], float2 y0, float
   }
 }
 
-template <int ST, bool TWO>
+// Writes the accumulated bins of a 16-wave sub-transform workgroup: acc[4 t + kd]
+// is bin k1 + R kk with kk = wave + 16 kb, kb = ka + 16 (4 row + t) + 256 kd.
+// Staged through LDS in bin order (the caller has passed a barrier after its
+// last use of xs), then stored as runs of R-strided bins.
+__device__ __forceinline__ void store_long_bins(const FusedArgs& a, const WorkItem& w,
+                                                float2* xs, const float (&acc)[16], int tid,
+                                                int k1, int R) {
+  const int lane = tid & 63, wave = tid >> 6;
+  float* st = reinterpret_cast<float*>(xs);
+  const int ka = lane & 15, row = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int kd = 0; kd < 4; ++kd)
+      st[wave + 16 * (ka + 16 * (4 * row + t) + 256 * kd)] = acc[4 * t + kd];
+  __syncthreads();
+  float* out = out_row(a, w);
+  const bool add = (w.chunks == 1) && a.accumulate;
+  for (int e = tid; e < 16 * SUB; e += 1024) {
+    float* dst = out + k1 + R * e;
+    *dst = add ? (*dst + st[e]) : st[e];
+  }
+}
+
+// Whether every code row of pulses [p0, p1) is binary (sign bits usable).
+__device__ __forceinline__ bool range_binary(const FusedArgs& a, int p0, int p1) {
+  if (!a.code_bits) return false;
+  if (!a.tx_per_pulse) return a.code_binary[0] != 0;
+  int all = 1;
+  for (int p = p0; p < p1; ++p) all &= a.code_binary[p];
+  return all != 0;
+}
+
+// TWO: L <= 2048 (see above).  Otherwise every pulse's 16 samples and codes
+// per thread are loaded at the start of its first pass; this variant runs the
+// pulse ranges whose codes are not all binary (fused_spectra_long_dma runs the
+// others, from the same grid).
+template <int ST, bool TWO, bool K0>
 __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
   using IO = SampleIO<ST>;
   __shared__ float2 xs[16 * XWAVE];
@@ -585,10 +631,11 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
 
   const int p0 = static_cast<int>((static_cast<int64_t>(c) * a.n_pulses) / w.chunks);
   const int p1 = static_cast<int>((static_cast<int64_t>(c + 1) * a.n_pulses) / w.chunks);
+  if (!TWO && range_binary(a, p0, p1)) return;  // the DMA variant's work item
 
-  float2 xpre[16];  // W_N^{1024 k1 j}: same for every thread
+  float2 xpre[16];  // W_N^{1024 k1 j}: same for every thread (unused with K0)
 #pragma unroll
-  for (int j = 0; j < 16; ++j) xpre[j] = tw[(1024 * k1 * j) & (N - 1)];
+  for (int j = 0; j < 16; ++j) xpre[j] = K0 ? make_float2(1.f, 0.f) : tw[(1024 * k1 * j) & (N - 1)];
   WaveTwiddles wt;
   load_wave_twiddles(wt, tw, N, k1 + R * wave, lane);
   const Dft16Consts dk = dft16_consts();
@@ -630,7 +677,7 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
       const float2 y0 = conj_mul(nc[0], IO::cvt(nr[0]));
       const float2 y1 = conj_mul(nc[1], IO::cvt(nr[1]));
       if (p + 1 < p1) fetch2(p + 1);
-      two_point_pass<ST>(v, y0, cmul(y1, xpre[1]), dk);
+      two_point_pass(v, y0, K0 ? y1 : cmul(y1, xpre[1]), dk);
     } else {
       const gptr<raw_t> srow = uniform_ptr(reinterpret_cast<const raw_t*>(a.samples) +
                                            (static_cast<int64_t>(p) * a.stride + gate_off));
@@ -643,7 +690,10 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
                    ? conj_mul(from_builtin(txp[n]), IO::cvt(from_builtin(srow[n])))
                    : make_float2(0.f, 0.f);
       }
-      dft16_pre1(v, xpre, dk);
+      if constexpr (K0)
+        dft16(v, dk);
+      else
+        dft16_pre1(v, xpre, dk);
     }
     __syncthreads();  // every wave has finished its exchanges of the previous pulse
 #pragma unroll
@@ -654,24 +704,178 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
     wave_lds_sync();  // read before this wave reuses its region for its own exchange
     wave_fft_accumulate(v, xw, wt, dk, acc, lane);
   }
+  __syncthreads();
+  store_long_bins(a, w, xs, acc, tid, k1, R);
+}
 
-  // acc[4 t + kd] is bin k1 + R kk with kk = wave + 16 kb,
-  // kb = ka + 16 (4 row + t) + 256 kd.
-  __syncthreads();
-  float* st = reinterpret_cast<float*>(xs);
-  const int ka = lane & 15, row = lane >> 4;
-#pragma unroll
-  for (int t = 0; t < 4; ++t)
-#pragma unroll
-    for (int kd = 0; kd < 4; ++kd)
-      st[wave + 16 * (ka + 16 * (4 * row + t) + 256 * kd)] = acc[4 * t + kd];
-  __syncthreads();
-  float* out = out_row(a, w);
-  const bool add = (w.chunks == 1) && a.accumulate;
-  for (int e = tid; e < 16 * SUB; e += 1024) {
-    float* dst = out + k1 + R * e;
-    *dst = add ? (*dst + st[e]) : st[e];
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void global_void_t;
+
+// One wave copies 4096 bytes from global memory straight into LDS: 16
+// instructions of one dword per lane, at byte 256 i + 4 lane of both the
+// source (g plus the lane's offset `lo` = 4 lane) and the LDS block l.
+template <int... I>
+__device__ __forceinline__ void wave_dma_4k(const char* g, uint32_t lo, char* l,
+                                            std::integer_sequence<int, I...>) {
+  (__builtin_amdgcn_global_load_lds((global_void_t*)(g + lo), (lds_void_t*)l, 4, 256 * I, 0), ...);
+}
+
+// One wave copies `bytes` (a multiple of 4, > 0) from src (uniform over the
+// wave) into LDS at dst.  The data is in LDS once the wave's vector-memory
+// counter has drained.
+__device__ __forceinline__ void wave_copy_to_lds(const char* src, char* dst, int bytes, int lane) {
+  const uint32_t lo = 4u * static_cast<uint32_t>(lane);
+  int done = 0;
+  for (; done + 4096 <= bytes; done += 4096) {
+    // the block's base as a wave-uniform (scalar) address
+    const uint64_t b = reinterpret_cast<uint64_t>(src + done);
+    const uint32_t blo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b));
+    const uint32_t bhi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(b >> 32));
+    const char* g = reinterpret_cast<const char*>((static_cast<uint64_t>(bhi) << 32) | blo);
+    wave_dma_4k(g, lo, dst + done, std::make_integer_sequence<int, 16>{});
   }
+  for (; done < bytes; done += 256)  // tail: only the lanes inside the range copy
+    if (static_cast<uint32_t>(done) + lo < static_cast<uint32_t>(bytes))
+      __builtin_amdgcn_global_load_lds((global_void_t*)(src + done + lo), (lds_void_t*)(dst + done),
+                                       4, 0, 0);
+}
+
+__device__ __forceinline__ void wait_lds_ops() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void wait_vmem_ops() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Code lengths 2048 < L <= 16384 with binary codes.  Sixteen waves share one
+// 16384-point sub-transform, so a workgroup fills the LDS of a compute unit
+// and no other workgroup hides its memory waits: loaded at the start of each
+// pulse, the pulse's samples and codes stall all sixteen waves together.  But
+// each wave's exchange region is free from the moment its pass-2 inputs are
+// read back until the next pulse's all-to-all exchange: wave w then copies
+// samples [1024 w, 1024 w + 1024) of the next pulse's gate window straight
+// into its region (LDS DMA), and after a barrier the first pass reads sample
+// lg + 1024 j from region j.  The codes (+-1, as most radar codes are) come as
+// one word of sign bits per thread and pulse, fetched with the samples.  Runs
+// the pulse ranges whose code rows are all binary (fused_spectra_long runs the
+// others, from the same grid).
+template <int ST, bool K0>
+__global__ void __launch_bounds__(1024) fused_spectra_long_dma(FusedArgs a) {
+  using IO = SampleIO<ST>;
+  using raw_t = typename IO::raw_t;
+  constexpr int SB = static_cast<int>(sizeof(raw_t));
+  __shared__ float2 xs[16 * XWAVE];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int R = 1 << a.log2_r;  // N / 16384
+  const WorkItem w = work_item(a, R);
+  const int g = w.g, k1 = w.zg, c = w.c;
+  if (g < 0) return;  // uniform over the workgroup, before any barrier
+  const int N = a.n_fft;
+  const int L = a.code_len;
+  const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
+
+  const int p0 = static_cast<int>((static_cast<int64_t>(c) * a.n_pulses) / w.chunks);
+  const int p1 = static_cast<int>((static_cast<int64_t>(c + 1) * a.n_pulses) / w.chunks);
+  if (!range_binary(a, p0, p1)) return;  // fused_spectra_long's work item
+
+  float2 xpre[16];  // W_N^{1024 k1 j}: same for every thread (unused with K0)
+#pragma unroll
+  for (int j = 0; j < 16; ++j) xpre[j] = K0 ? make_float2(1.f, 0.f) : tw[(1024 * k1 * j) & (N - 1)];
+  WaveTwiddles wt;
+  load_wave_twiddles(wt, tw, N, k1 + R * wave, lane);
+  const Dft16Consts dk = dft16_consts();
+
+  float acc[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+
+  const int64_t gate_off = static_cast<int64_t>(a.first_gate) + static_cast<int64_t>(g) * a.gate_step;
+  float2* xw = xs + wave * XWAVE;
+
+  // this wave's share of a pulse's gate window: samples [1024 wave, + cnt);
+  // the rest of the region (all of it past the code) reads as zero samples
+  const int cnt = max(0, min(SUB, L - SUB * wave));
+  auto prefetch = [&](int p) {
+    if (cnt > 0)
+      wave_copy_to_lds(static_cast<const char*>(a.samples) +
+                           (static_cast<int64_t>(p) * a.stride + gate_off + SUB * wave) * SB,
+                       reinterpret_cast<char*>(xw), cnt * SB, lane);
+    if (cnt < SUB) {
+      raw_t* rw = reinterpret_cast<raw_t*>(xw);
+      for (int e = cnt + lane; e < SUB; e += 64) rw[e] = IO::zero();
+    }
+  };
+  // sign bits of pulse p's codes
+  auto fetch_bits = [&](int p) {
+    return static_cast<uint32_t>(
+        a.code_bits[static_cast<int64_t>(a.tx_per_pulse ? p : 0) * CODE_BITS_WORDS + tid]);
+  };
+  uint32_t cbits = 0, nbits = 0;
+  if (p0 < p1) {
+    prefetch(p0);
+    cbits = fetch_bits(p0);
+  }
+  wait_vmem_ops();
+  __syncthreads();
+
+  for (int p = p0; p < p1; ++p) {
+    float2 v[16];
+    // conj(c) x with c = +-1: the sign bit of both parts flips where c = -1
+    // (past the code the bits are clear and the samples zero)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float2 x = IO::cvt(reinterpret_cast<const raw_t*>(xs + j * XWAVE)[tid]);
+      const uint32_t sgn = (cbits << (31 - j)) & 0x80000000u;
+      v[j] = make_float2(__uint_as_float(__float_as_uint(x.x) ^ sgn),
+                         __uint_as_float(__float_as_uint(x.y) ^ sgn));
+    }
+    if constexpr (K0)
+      dft16(v, dk);
+    else
+      dft16_pre1(v, xpre, dk);
+    __syncthreads();  // every thread has read the sample regions
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xs[k * XWAVE + tid] = v[k];  // region k: U_k[lg]
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = xw[lane + 64 * j];    // U_wave[lane + 64 j]
+    wave_lds_sync();  // read before this wave reuses its region for its own exchange
+    const bool more = p + 1 < p1;
+    wave_fft_accumulate(v, xw, wt, dk, acc, lane, [&] {
+      if (more) {
+        wait_lds_ops();  // the region's last reads are served before the copy lands
+        prefetch(p + 1);
+        nbits = fetch_bits(p + 1);
+      }
+    });
+    cbits = nbits;
+    wait_vmem_ops();  // this wave's copy has landed
+    __syncthreads();  // every region holds the next pulse's samples
+  }
+  store_long_bins(a, w, xs, acc, tid, k1, R);
+}
+
+// Sign bits of binary codes: one workgroup of SUB threads per code row;
+// thread lg packs code[lg + SUB j], j < 16, and the workgroup decides whether
+// the whole row is +-1 + 0i.
+__global__ void __launch_bounds__(1024)
+pack_code_bits(const float2* __restrict__ tx, int32_t code_len, uint16_t* __restrict__ bits,
+               int32_t* __restrict__ binary) {
+  const int row = blockIdx.x, lg = threadIdx.x;
+  const float2* c = tx + static_cast<int64_t>(row) * code_len;
+  uint32_t word = 0;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int n = lg + SUB * j;
+    if (n < code_len) {
+      const float2 v = c[n];
+      ok = ok && (v.x == 1.f || v.x == -1.f) && v.y == 0.f;
+      word |= (v.x < 0.f ? 1u : 0u) << j;
+    }
+  }
+  bits[static_cast<int64_t>(row) * CODE_BITS_WORDS + lg] = static_cast<uint16_t>(word);
+  const int all = __syncthreads_and(ok ? 1 : 0);
+  if (lg == 0) binary[row] = all ? 1 : 0;
 }
 
 // S = sum over chunks of the partial spectra (fixed order), for every gate or
@@ -836,12 +1040,29 @@ hipError_t launch_fused_t(const FusedArgs& a, hipStream_t stream) {
 template <int ST>
 hipError_t launch_fused_long_t(const FusedArgs& a, hipStream_t stream) {
   const int64_t blocks = fused_blocks(a, 1 << a.log2_r);
-  if (a.code_len <= 2 * SUB)
-    hipLaunchKernelGGL((fused_spectra_long<ST, true>), dim3(static_cast<unsigned>(blocks)),
-                       dim3(1024), 0, stream, a);
+  const dim3 grid(static_cast<unsigned>(blocks)), block(1024);
+  const bool two = a.code_len <= 2 * SUB, k0 = a.log2_r == 0;
+  if (two) {
+    if (k0)
+      hipLaunchKernelGGL((fused_spectra_long<ST, true, true>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((fused_spectra_long<ST, true, false>), grid, block, 0, stream, a);
+    return hipGetLastError();
+  }
+  // work items whose codes are all binary run in the DMA variant, the others
+  // in the plain one; each workgroup of either grid decides for itself
+  if (a.code_bits) {
+    if (k0)
+      hipLaunchKernelGGL((fused_spectra_long_dma<ST, true>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((fused_spectra_long_dma<ST, false>), grid, block, 0, stream, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (k0)
+    hipLaunchKernelGGL((fused_spectra_long<ST, false, true>), grid, block, 0, stream, a);
   else
-    hipLaunchKernelGGL((fused_spectra_long<ST, false>), dim3(static_cast<unsigned>(blocks)),
-                       dim3(1024), 0, stream, a);
+    hipLaunchKernelGGL((fused_spectra_long<ST, false, false>), grid, block, 0, stream, a);
   return hipGetLastError();
 }
 
@@ -882,6 +1103,13 @@ hipError_t launch_reduce_chunks(const float* partial, float* spectra, int64_t el
                                 const int32_t* list, const int32_t* count, hipStream_t stream) {
   hipLaunchKernelGGL(reduce_chunks, dim3(grid_for(elems)), dim3(256), 0, stream, partial,
                      spectra, elems, chunks, accumulate, n_fft, list, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_code_bits(const float* tx, int32_t rows, int32_t code_len,
+                                 uint16_t* bits, int32_t* binary, hipStream_t stream) {
+  hipLaunchKernelGGL(pack_code_bits, dim3(static_cast<unsigned>(rows)), dim3(SUB), 0, stream,
+                     reinterpret_cast<const float2*>(tx), code_len, bits, binary);
   return hipGetLastError();
 }
 

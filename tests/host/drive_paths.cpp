@@ -275,6 +275,8 @@ int main() {
       {256, 1024, 64, 100, ISPL_SAMPLES_C64, 25},     // zoom workload, coarse length
       {1000, 16384, 37, 30, ISPL_SAMPLES_CI16, 0},    // realistic code and transform
       {2000, 32768, 5, 7, ISPL_SAMPLES_C64, 3},       // long code: sixteen-wave sub-transforms
+      {16384, 16384, 3, 4, ISPL_SAMPLES_C64, 25},     // the paper's code: sign bits, LDS prefetch
+      {5000, 32768, 2, 9, ISPL_SAMPLES_CI16, 1},      // long code, partly filled last region
       {1024, 2048, 3, 1, ISPL_SAMPLES_CI16, 1},       // L = SUB, one pulse
       {1, 1024, 1, 2, ISPL_SAMPLES_C64, 0},           // one sample, one gate
       {300, 4096, 700, 80, ISPL_SAMPLES_CI16, 5},     // many gates, one-wave tiles
@@ -288,6 +290,7 @@ int main() {
   lzoom_path({256, 16384, 700, 300, ISPL_SAMPLES_CI16, 0}, 256, ISPL_ZOOM_FP16X3);
   lzoom_path({500, 8192, 9, 13, ISPL_SAMPLES_C64, 2}, 128, ISPL_ZOOM_BF16X3);
   stream_path({1000, 16384, 37, 30, ISPL_SAMPLES_CI16, 0}, 10, 3);
+  stream_path({4000, 16384, 3, 20, ISPL_SAMPLES_C64, 25}, 4, 2);
   stream_path({256, 1024, 64, 100, ISPL_SAMPLES_C64, 25}, 7, 2);
   for (void* p : g_bufs) (void)hipFree(p);
   const int me = mock_errors();

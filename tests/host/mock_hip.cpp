@@ -448,6 +448,12 @@ hipError_t launch_fused(const FusedArgs& a, hipStream_t st) {
     }
     if (c.chunks < 1) mock_fail("fused: no pulse chunk");
     check_range(c.twiddle, size_t(c.n_fft) * 8, "fused twiddle");
+    if (c.code_bits) {  // sign bits of every code row the launch reads
+      if (c.code_len <= 2 * SUB) mock_fail("fused: code bits for a code of at most 2 SUB");
+      const size_t rows = c.tx_per_pulse ? size_t(c.n_pulses) : 1;
+      check_range(c.code_bits, rows * CODE_BITS_WORDS * 2, "fused code bits");
+      check_range(c.code_binary, rows * 4, "fused code flags");
+    }
     if (c.adapt_target > 0) {  // chunk count from the list length, rows by list slot
       if (!c.gate_list) mock_fail("fused: adaptive chunking without a list");
       const int zg = c.sub_len == SUB ? R / c.waves_per_block : R;
@@ -494,6 +500,16 @@ hipError_t launch_reduce_chunks(const float* partial, float* spectra, int64_t el
     const std::vector<int> gs = active_gates(list, count, G, G);
     for (int k = 0; k < chunks; ++k) check_rows(partial + k * elems, n_fft, gs, "reduce partial");
     check_rows(spectra, n_fft, gs, "reduce spectra");
+  });
+  return hipSuccess;
+}
+hipError_t launch_pack_code_bits(const float* tx, int32_t rows, int32_t code_len, uint16_t* bits,
+                                 int32_t* binary, hipStream_t st) {
+  run_on(st, [=] {
+    if (rows < 1 || code_len < 1 || code_len > 16 * SUB) mock_fail("pack code bits: geometry");
+    check_range(tx, size_t(rows) * code_len * 8, "pack tx");
+    check_range(bits, size_t(rows) * CODE_BITS_WORDS * 2, "pack bits");
+    check_range(binary, size_t(rows) * 4, "pack flags");
   });
   return hipSuccess;
 }

@@ -83,6 +83,12 @@ SHAPES = [
     # the two-slice variant (L <= 2048) at its edge, and one sample past it
     (16384, 2048, 2, 5, 9, 2, "c64", True, "gauss"),
     (16384, 2049, 2, 3, 9, 0, "ci16", False, "bpsk"),
+    # binary codes past 2048 samples: the LDS-prefetch variant with sign bits
+    # (whole code, partly filled last region, shared code, two bin classes)
+    (16384, 16384, 3, 4, 25, 0, "c64", True, "bpsk"),
+    (16384, 3000, 2, 5, 7, 0, "c64", False, "bpsk"),
+    (32768, 5000, 3, 3, 25, 1, "ci16", True, "bpsk"),
+    (16384, 9217, 2, 3, 11, 4, "ci16", True, "bpsk"),
 ]
 
 
@@ -104,6 +110,51 @@ def test_shapes_match_oracle(ispl, shape):
     check_peaks(bins.cpu().numpy(), ref, ref_bins)
     ctx.close()
 
+
+
+def test_long_code_binary_and_complex_rows(ispl):
+    """Per-pulse codes of 5000 samples, some rows +-1 and some complex, over
+    pulse chunks: chunks whose rows are all binary run in the LDS-prefetch
+    variant with sign bits, the others in the plain variant, from one call;
+    the spectra match the oracle element by element."""
+    N, L, G, P, s, g0 = 16384, 5000, 3, 40, 25, 0
+    stride = g0 + (G - 1) * s + L + 3
+    samples, tx = random_inputs(P, stride, L, sample_type="c64", code_kind="bpsk", seed=77)
+    _, phase = random_inputs(P, stride, L, sample_type="c64", code_kind="phase", seed=78)
+    tx = tx.copy()
+    tx[16:24] = phase[16:24]     # pulses 16..23 complex, the rest binary
+    tx[31, 4999] = 1.0 + 0.5j    # one complex chip in an otherwise binary row
+    plan = ispl.plan(P, code_len=L, fft_len=N, n_gates=G, gate_step=s, first_gate=g0,
+                     pulse_stride=stride, sample_type="c64", max_pulses=P)
+    say(f"case binary/complex rows, plan {plan}")
+    assert plan["chunks"] > 2
+    ctx, out, *_ = gpu_spectra(ispl, samples, tx, L=L, N=N, G=G, s=s, g0=g0, stride=stride,
+                               st="c64")
+    ref = oracle_spectra(samples, tx, n_gates=G, gate_step=s, first_gate=g0, fft_len=N,
+                         tx_per_pulse=True)
+    assert_spectra_match(out.cpu().numpy(), ref, what="binary and complex code rows")
+    ctx.close()
+
+
+@pytest.mark.parametrize("st,L,N", [("c64", 16384, 16384), ("ci16", 7000, 32768)])
+def test_long_code_sign_bits_equal_complex_codes(ispl, st, L, N):
+    """+-1 codes read as sign bits (the context's LDS-prefetch variant) and as
+    complex numbers (the entry point without a context has no sign-bit buffer)
+    give the same spectra bit for bit: conj(c) x with c = +-1 is an exact sign
+    change either way."""
+    G, P, s = 3, 6, 25
+    stride = (G - 1) * s + L
+    samples, tx = random_inputs(P, stride, L, sample_type=st, code_kind="bpsk", seed=L + N,
+                                amplitude=3000.0 if st == "ci16" else 1.0)
+    say(f"case sign bits vs complex codes {st} L={L} N={N}")
+    ctx, out, xs, xt = gpu_spectra(ispl, samples, tx, L=L, N=N, G=G, s=s, g0=0, stride=stride,
+                                   st=st)
+    other = torch.empty_like(out)
+    ispl.integrate_spectra_noalloc(xs, xt, other, code_len=L, fft_len=N, n_gates=G, gate_step=s,
+                                   pulse_stride=stride, sample_type=st, max_pulses=P)
+    torch.cuda.synchronize()
+    assert torch.equal(out, other)
+    ctx.close()
 
 def test_small_workload_full(ispl):
     cfg = CONFIGS["small"]
