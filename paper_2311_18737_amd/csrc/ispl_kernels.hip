@@ -33,6 +33,7 @@
 #include <algorithm>
 #include <math.h>
 #include <stdint.h>
+#include <type_traits>
 #include <utility>
 
 #include "ispl_internal.h"
@@ -261,6 +262,60 @@ struct SampleIO<1> {  // int16 (re, im) pairs; int16 -> float is exact
   }
 };
 
+// DFT4 of (a0, T a1, T^2 a2, T^3 a3), twiddles in geometric progression: with
+// t02 = a0 + T^2 a2 and t13 = a1 + T^2 a3 the outputs are t02 +- T t13 and
+// (a0 - T^2 a2) -+ i T (a1 - T^2 a3), so only T and T^2 are needed and every
+// product folds into a multiply-add (24 operations, as for three free twiddles).
+__device__ __forceinline__ void dft4_geo(float2& a0, float2& a1, float2& a2, float2& a3, float2 t,
+                                         float2 t2) {
+  const float2 t02 = cmuladd(a0, t2, a2);
+  const float2 d02 = twice_minus(a0, t02);
+  const float2 t13 = cmuladd(a1, t2, a3);
+  const float2 u13 = twice_minus(a1, t13);
+  a0 = cmuladd(t02, t, t13);
+  a2 = twice_minus(t02, a0);
+  a1 = cmuladd(d02, make_float2(t.y, -t.x), u13);  // -i T
+  a3 = twice_minus(d02, a1);
+}
+
+// Twiddles of a 16-point DFT whose inputs carry the factors P^j (j < 16):
+// with j = j1 + 4 j2 the first stage is a DFT4 over j2 with ratio G = P^4, the
+// second a DFT4 over j1 with ratio H_k1 = P W_16^{k1}; each as (ratio, ratio^2).
+struct GeoTwiddles {
+  float2 g, g2;
+  float2 h[4], h2[4];
+};
+
+// sum_j v[j] P^j W_16^{j k} into v[k], for the progression of `w`.
+__device__ __forceinline__ void dft16_geo(float2 (&v)[16], const GeoTwiddles& w) {
+#pragma unroll
+  for (int j1 = 0; j1 < 4; ++j1) dft4_geo(v[j1], v[j1 + 4], v[j1 + 8], v[j1 + 12], w.g, w.g2);
+  // v[j1 + 4 k1] holds the first-stage output k1 of group j1
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1)
+    dft4_geo(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3], w.h[k1], w.h2[k1]);
+  // position 4 k1 + k2 holds X[k1 + 4 k2]
+  float2 t[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) t[i] = v[4 * (i & 3) + (i >> 2)];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = t[i];
+}
+
+// GeoTwiddles of the progression P = W_N^e (all from the table, so every
+// factor is correctly rounded): G = W_N^{4 e}, H_k1 = W_N^{e + k1 N / 16}.
+__device__ __forceinline__ void load_geo(GeoTwiddles& w, const float2* __restrict__ tw, int n_fft,
+                                         int e) {
+  const int nmask = n_fft - 1, n16 = n_fft >> 4;
+  w.g = tw[(4 * e) & nmask];
+  w.g2 = tw[(8 * e) & nmask];
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    w.h[k1] = tw[(e + k1 * n16) & nmask];
+    w.h2[k1] = tw[(2 * e + 2 * k1 * n16) & nmask];
+  }
+}
+
 // Twiddles of one wave's 1024-point transform of bin class kappa: the wave
 // produces bins kappa + S kb (S = N / 1024, kb < 1024) of the N-point
 // spectrum, so its input carries the factor W_N^{kappa n} on top of the
@@ -286,6 +341,41 @@ __device__ __forceinline__ void load_wave_twiddles(WaveTwiddles& w, const float2
     for (int r = 1; r < 4; ++r) w.tw3[t][r - 1] = tw[((n_fft >> 6) * r * (4 * row + t)) & nmask];
 }
 
+// The same transform with passes 2 and 3 in geometric form (36 instead of 56
+// registers of per-lane twiddles; the long-code kernels need the room).  With
+// q = kappa + S ka, lane (ka, r) weighs u_ka[r + 4 m] in pass 2 by
+// W_N^{(r + 4 m) q} = W_N^{r q} (W_N^{4 q})^m: a progression of ratio W_N^{4 q},
+// whose common factor W_N^{r q} moves into pass 3, where the 4-point DFT over r
+// then weighs term r by (W_N^{q} W_64^{kc})^r = T_kc^r, T_kc = W_N^{q + 16 S kc},
+// kc = 4 row + t.
+struct WaveTwiddlesGeo {
+  float2 pre[16];            // pass 1, as above
+  GeoTwiddles p2;            // pass 2: progression W_N^{4 q}
+  float2 t3[4], t3sq[4];     // pass 3: T_kc and T_kc^2
+};
+
+__device__ __forceinline__ void load_wave_twiddles(WaveTwiddlesGeo& w,
+                                                   const float2* __restrict__ tw, int n_fft,
+                                                   int kappa, int lane) {
+  const int nmask = n_fft - 1, S = n_fft >> 10;
+  const int ka = lane & 15, row = lane >> 4;
+  const int q = kappa + S * ka;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) w.pre[j] = tw[(64 * kappa * j) & nmask];
+  load_geo(w.p2, tw, n_fft, 4 * q);
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int e = q + 16 * S * (4 * row + t);
+    w.t3[t] = tw[e & nmask];
+    w.t3sq[t] = tw[(2 * e) & nmask];
+  }
+}
+
+template <typename TW>
+constexpr bool kGeo = false;
+template <>
+constexpr bool kGeo<WaveTwiddlesGeo> = true;
+
 // One wave's 1024-point transform and power accumulation.  On entry lane l
 // holds f[l + 64 j] in v[j]; xw is the wave's exchange buffer.  On exit
 // acc[4 t + kd] += |F[kb]|^2 for kb = ka + 16 (4 row + t) + 256 kd, with
@@ -298,9 +388,8 @@ struct NoHook {
 
 // `after_exchange` runs right after this wave has issued the reads of its
 // pass-2 inputs: from then until the next call the exchange buffer is free.
-template <bool K0 = false, bool F4 = false, typename Hook = NoHook>
-__device__ __forceinline__ void wave_fft_accumulate(float2 (&v)[16], float2* xw,
-                                                    const WaveTwiddles& w,
+template <bool K0 = false, bool F4 = false, typename TW = WaveTwiddles, typename Hook = NoHook>
+__device__ __forceinline__ void wave_fft_accumulate(float2 (&v)[16], float2* xw, const TW& w,
                                                     const Dft16Consts& dk, float (&acc)[16],
                                                     int lane, Hook after_exchange = Hook{}) {
   const int ka = lane & 15, row = lane >> 4;
@@ -322,7 +411,10 @@ __device__ __forceinline__ void wave_fft_accumulate(float2 (&v)[16], float2* xw,
 #pragma unroll
   for (int m = 0; m < 16; ++m) v[m] = xw[p2base + 4 * m];
   after_exchange();
-  dft16_pre(v, w.tw2, dk);
+  if constexpr (kGeo<TW>)
+    dft16_geo(v, w.p2);
+  else
+    dft16_pre(v, w.tw2, dk);
 
   // pass 3: the 4-point DFT over r runs across the four 16-lane rows.  For
   // each t a row transpose hands row g the four values v_{ka,r}[4 g + t],
@@ -335,7 +427,10 @@ __device__ __forceinline__ void wave_fft_accumulate(float2 (&v)[16], float2* xw,
     row_transpose4(im);
     float2 c0 = make_float2(re[0], im[0]), c1 = make_float2(re[1], im[1]);
     float2 c2 = make_float2(re[2], im[2]), c3 = make_float2(re[3], im[3]);
-    dft4_w123(c0, c1, c2, c3, w.tw3[t][0], w.tw3[t][1], w.tw3[t][2]);
+    if constexpr (kGeo<TW>)
+      dft4_geo(c0, c1, c2, c3, w.t3[t], w.t3sq[t]);
+    else
+      dft4_w123(c0, c1, c2, c3, w.tw3[t][0], w.tw3[t][1], w.tw3[t][2]);
     acc[4 * t + 0] = fmaf(c0.y, c0.y, fmaf(c0.x, c0.x, acc[4 * t + 0]));
     acc[4 * t + 1] = fmaf(c1.y, c1.y, fmaf(c1.x, c1.x, acc[4 * t + 1]));
     acc[4 * t + 2] = fmaf(c2.y, c2.y, fmaf(c2.x, c2.x, acc[4 * t + 2]));
@@ -450,7 +545,10 @@ __global__ void __launch_bounds__(64 * RW) fused_spectra(FusedArgs a) {
   const int p0 = static_cast<int>((static_cast<int64_t>(c) * a.n_pulses) / w.chunks);
   const int p1 = static_cast<int>((static_cast<int64_t>(c + 1) * a.n_pulses) / w.chunks);
 
-  WaveTwiddles wt;
+  // the geometric form where its lower register count lets eight-wave
+  // workgroups keep four waves per SIMD (measured: N = 8192 16 % faster; at
+  // 16, 4 and 1 waves the original form is as fast or faster)
+  std::conditional_t<RW == 8, WaveTwiddlesGeo, WaveTwiddles> wt;
   load_wave_twiddles(wt, tw, a.n_fft, k1, lane);
   const Dft16Consts dk = dft16_consts();
 
@@ -636,7 +734,7 @@ __global__ void __launch_bounds__(1024) fused_spectra_long(FusedArgs a) {
   float2 xpre[16];  // W_N^{1024 k1 j}: same for every thread (unused with K0)
 #pragma unroll
   for (int j = 0; j < 16; ++j) xpre[j] = K0 ? make_float2(1.f, 0.f) : tw[(1024 * k1 * j) & (N - 1)];
-  WaveTwiddles wt;
+  WaveTwiddlesGeo wt;  // the form that leaves these kernels room
   load_wave_twiddles(wt, tw, N, k1 + R * wave, lane);
   const Dft16Consts dk = dft16_consts();
 
@@ -780,7 +878,7 @@ __global__ void __launch_bounds__(1024) fused_spectra_long_dma(FusedArgs a) {
   float2 xpre[16];  // W_N^{1024 k1 j}: same for every thread (unused with K0)
 #pragma unroll
   for (int j = 0; j < 16; ++j) xpre[j] = K0 ? make_float2(1.f, 0.f) : tw[(1024 * k1 * j) & (N - 1)];
-  WaveTwiddles wt;
+  WaveTwiddlesGeo wt;  // the form that leaves these kernels room
   load_wave_twiddles(wt, tw, N, k1 + R * wave, lane);
   const Dft16Consts dk = dft16_consts();
 
