@@ -395,8 +395,11 @@ void ispl_destroy(ispl_ctx* ctx);
  *   ispl_batch_get_plan / set_plan  the plan in use (waves 0 and chunks 0 mean
  *                       the automatic choice; waves only for modes with
  *                       L <= 1024: a power of two <= min(16, N/1024)).
- * Waves per workgroup do not change any result; pulse chunks change the
- * summation order (results within rounding).  The object owns one context per
+ * Waves per workgroup change no result between shapes that share a twiddle
+ * factorization (eight-wave workgroups use a geometric form of the inner
+ * passes' twiddles, every other shape the direct form) and only the rounding
+ * across the two; pulse chunks change the summation order (results within
+ * rounding).  The object owns one context per
  * mode and its streams; calls on one object must not overlap.
  */
 typedef struct ispl_batch ispl_batch;

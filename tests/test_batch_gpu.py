@@ -5,8 +5,10 @@ lengths 128, 480, 1000, 2000; FFT lengths 4096 ... 32768, the last one with
 the long-code transform).  Under the automatic plan every mode runs exactly
 its ispl_integrate_spectra launches, so the batch must reproduce them bit for
 bit, from its graph (parallel or serial branches) and from direct launches;
-other waves per workgroup must not change a bit, other pulse chunks only the
-rounding; against the FP64 oracle every mode meets the plain path's 1e-5 bound.
+other waves per workgroup change nothing between tile shapes of one twiddle
+form and only the rounding between forms (eight-wave workgroups take the
+geometric form), other pulse chunks only the rounding; against the FP64 oracle
+every mode meets the plain path's 1e-5 bound.
 """
 
 import sys
@@ -143,13 +145,20 @@ def test_hand_set_plans(ispl):
     inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
     ref = per_mode(ispl, geo, data, "c64")
     b = ispl.Batch(geo)
+    auto_waves = [min(g["fft_len"] // 1024, 16) for g in geo]  # the automatic tile shapes
     # other tile shapes (waves per workgroup) and serial branches: bit for bit
+    # within a twiddle form (eight waves: geometric passes 2-3), to rounding
+    # across forms
     for waves, serial in (([2, 4, 8, 0], False), ([1, 1, 2, 0], True), ([4, 8, 16, 0], False)):
         b.set_plan(order=[3, 2, 1, 0], waves=waves, serial=serial)
         outs = b.integrate(inputs)
         torch.cuda.synchronize()
-        for o, r in zip(outs, ref):
-            assert torch.equal(o, r), (waves, serial)
+        for w, aw, o, r in zip(waves, auto_waves, outs, ref):
+            if w == 0 or (w == 8) == (aw == 8):
+                assert torch.equal(o, r), (waves, serial)
+            else:
+                scale = torch.maximum(r, r.mean(dim=1, keepdim=True))
+                assert float(((o - r).abs() / torch.clamp(scale, min=1e-30)).max()) <= 2e-6
     for bad in (dict(order=[0, 0, 1, 2]), dict(waves=[3, 0, 0, 0]), dict(waves=[0, 0, 0, 8]),
                 dict(waves=[8, 0, 0, 0]), dict(chunks=[0, 0, 0, 10 ** 6])):
         with pytest.raises(ispl.IsplError):
