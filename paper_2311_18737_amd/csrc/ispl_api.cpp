@@ -1128,7 +1128,6 @@ struct ispl_lzoom {
   int32_t* fallback_list; // [G]
   int32_t* counts;        // [2]: zoomed, fallback
   int32_t* done;          // completion counter of the decision (zero between calls)
-  int32_t* fb_slot;       // [G]: position of each fallback gate in the fallback list
   float* fb_partial;      // [fb_rows][N]: chunk partials of the fallback launch
   int32_t fb_rows;
 };
@@ -1138,7 +1137,7 @@ namespace {
 void lzoom_free(ispl_lzoom* z) {
   void* bufs[] = {z->coarse_spectra, z->logits, z->confidence, z->window_spectra,
                   z->full_spectra, z->bin_start, z->flag, z->zoom_list, z->fallback_list,
-                  z->counts, z->done, z->fb_slot, z->fb_partial};
+                  z->counts, z->done, z->fb_partial};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   if (z->zoom) ispl_zoom_destroy(z->zoom);
@@ -1203,7 +1202,6 @@ ispl_status ispl_lzoom_create(const ispl_config* cfg, ispl_net* net, int32_t win
               {reinterpret_cast<void**>(&z->fallback_list), 4 * G},
               {reinterpret_cast<void**>(&z->counts), 8},
               {reinterpret_cast<void**>(&z->done), 4},
-              {reinterpret_cast<void**>(&z->fb_slot), 4 * G},
               {reinterpret_cast<void**>(&z->fb_partial), int64_t{4} * z->fb_rows * cfg->fft_len}};
   for (auto& w : want) {
     const hipError_t e = hipMalloc(w.p, static_cast<size_t>(w.bytes));
@@ -1275,7 +1273,7 @@ ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx
     pe.n_pulses = fp16 ? n_pulses : 0;
     e = ispl::launch_select_and_exponents(z->logits, G, c.fft_len, z->window_bins, z->threshold,
                                           z->bin_start, z->confidence, z->flag, z->zoom_list,
-                                          z->fallback_list, z->counts, z->done, z->fb_slot, pe,
+                                          z->fallback_list, z->counts, z->done, pe,
                                           s);
   }
   if (e != hipSuccess) return hip_fail(e, "learned-zoom network launch");
@@ -1295,15 +1293,14 @@ ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx
   if (st != ISPL_OK) return st;
   ispl::FallbackChunks fc{};
   fc.counts = z->counts;
-  fc.slot = z->fb_slot;
   fc.partial = z->fb_partial;
   fc.zgroups = adaptive_zgroups(c);
   fc.target = fb.target;
   fc.max_chunks = fb.max_chunks;
   fc.rows = fb.rows;
   e = ispl::launch_split_peaks(z->window_spectra, z->zoom->partial, zoom_chunks, z->full_spectra,
-                               fc, z->flag, z->bin_start, G, z->window_bins, c.fft_len, peak_bin,
-                               peak_power, s);
+                               fc, z->zoom_list, z->fallback_list, z->bin_start, G,
+                               z->window_bins, c.fft_len, peak_bin, peak_power, s);
   if (e != hipSuccess) return hip_fail(e, "learned-zoom peak launch");
   return ok();
 }

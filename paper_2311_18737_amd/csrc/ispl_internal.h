@@ -206,15 +206,15 @@ hipError_t launch_select_windows(const float* logits, int32_t n_gates, int32_t f
 // rule's parameters.
 struct FallbackChunks {
   const int32_t* counts;  // [2]: zoomed, fallback
-  const int32_t* slot;    // [G]: position of a fallback gate in the fallback list
   const float* partial;   // [rows][N]
   int32_t zgroups, target, max_chunks, rows;
 };
 hipError_t launch_split_peaks(float* window_spectra, const float* window_partial,
                               int32_t zoom_chunks, float* full_spectra, const FallbackChunks& fb,
-                              const int32_t* flag, const int32_t* bin_start, int32_t n_gates,
-                              int32_t window_bins, int32_t fine_len, int32_t* peak_bin,
-                              float* peak_power, hipStream_t s);
+                              const int32_t* zoom_list, const int32_t* fallback_list,
+                              const int32_t* bin_start, int32_t n_gates, int32_t window_bins,
+                              int32_t fine_len, int32_t* peak_bin, float* peak_power,
+                              hipStream_t s);
 // Per-pulse FP16 exponents of the zoom DFT (pulses 0 .. n_pulses - 1).
 struct PulseExpArgs {
   const void* samples;
@@ -224,13 +224,11 @@ struct PulseExpArgs {
   int32_t sample_type, code_len, tx_per_pulse, n_pulses;
 };
 // select_windows and, in the same launch, the pulse exponents (n_pulses = 0: none).
-// fb_slot (device int32 [n_gates]) receives each fallback gate's position in
-// the fallback list (-1 for zoomed gates).
 hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int32_t fine_len,
                                        int32_t window_bins, float threshold, int32_t* bin_start,
                                        float* confidence, int32_t* flag, int32_t* zoom_list,
                                        int32_t* fallback_list, int32_t* counts, int32_t* done,
-                                       int32_t* fb_slot, const PulseExpArgs& pe, hipStream_t s);
+                                       const PulseExpArgs& pe, hipStream_t s);
 hipError_t launch_window_peak(const float* spectra, int32_t n_gates, int32_t window_bins,
                               int32_t fine_len, const int32_t* bin_start, const int32_t* list,
                               const int32_t* count, int32_t* peak_bin, float* peak_power,

@@ -71,11 +71,8 @@ __device__ float block_sum(float x, float* red) {
 
 // Ordered compaction of the flags into the zoomed and fallback gate lists by
 // one workgroup of NT threads sweeping the gates in order.
-// fb_slot (nullable) receives the position of each fallback gate in its list
-// and -1 for zoomed gates.
 __device__ void compact_gates(const int32_t* flag, int32_t n_gates, int32_t* zoom_list,
-                              int32_t* fallback_list, int32_t* counts, int32_t* fb_slot,
-                              int* wtot) {
+                              int32_t* fallback_list, int32_t* counts, int* wtot) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   int done_zoom = 0;  // zoomed gates before this sweep step (uniform)
   for (int b0 = 0; b0 < n_gates; b0 += NT) {
@@ -97,7 +94,6 @@ __device__ void compact_gates(const int32_t* flag, int32_t n_gates, int32_t* zoo
       zoom_list[zi] = g;
     else if (live)
       fallback_list[g - zi] = g;
-    if (fb_slot && live) fb_slot[g] = z ? -1 : g - zi;
     done_zoom += all;
   }
   if (tid == 0) {
@@ -115,7 +111,7 @@ __device__ __forceinline__ void select_window_block(
     int32_t window_bins, float threshold, int32_t* __restrict__ bin_start,
     float* __restrict__ confidence, int32_t* __restrict__ flag, int32_t* __restrict__ zoom_list,
     int32_t* __restrict__ fallback_list, int32_t* __restrict__ counts,
-    int32_t* __restrict__ done, int32_t* __restrict__ fb_slot) {
+    int32_t* __restrict__ done) {
   __shared__ int is_last;
   __shared__ int wtot[NT / 64];
   __shared__ float sv[NT / 64];
@@ -177,7 +173,7 @@ __device__ __forceinline__ void select_window_block(
   __syncthreads();
   if (!is_last) return;
   __threadfence();  // acquire every other workgroup's flag
-  compact_gates(flag, n_gates, zoom_list, fallback_list, counts, fb_slot, wtot);
+  compact_gates(flag, n_gates, zoom_list, fallback_list, counts, wtot);
   if (j == 0) *done = 0;
 }
 
@@ -189,7 +185,7 @@ select_windows(const float* __restrict__ logits, int32_t n_gates, int32_t fine_l
                int32_t* __restrict__ counts, int32_t* __restrict__ done) {
   select_window_block(static_cast<int>(blockIdx.x), logits, n_gates, fine_len, window_bins,
                       threshold, bin_start, confidence, flag, zoom_list, fallback_list, counts,
-                      done, nullptr);
+                      done);
 }
 
 // The window decision (workgroups g < n_gates) and, in the same launch, the
@@ -199,13 +195,12 @@ select_and_exponents(const float* __restrict__ logits, int32_t n_gates, int32_t 
                      int32_t window_bins, float threshold, int32_t* __restrict__ bin_start,
                      float* __restrict__ confidence, int32_t* __restrict__ flag,
                      int32_t* __restrict__ zoom_list, int32_t* __restrict__ fallback_list,
-                     int32_t* __restrict__ counts, int32_t* __restrict__ done,
-                     int32_t* __restrict__ fb_slot, PulseExpArgs pe) {
+                     int32_t* __restrict__ counts, int32_t* __restrict__ done, PulseExpArgs pe) {
   static_assert(NT == 256, "the exponent role runs 256 threads");
   const int b = static_cast<int>(blockIdx.x);
   if (b < n_gates) {
     select_window_block(b, logits, n_gates, fine_len, window_bins, threshold, bin_start,
-                        confidence, flag, zoom_list, fallback_list, counts, done, fb_slot);
+                        confidence, flag, zoom_list, fallback_list, counts, done);
   } else {
     pulse_exponent_block(pe.samples, pe.sample_type, pe.tx, pe.stride, pe.lo, pe.hi, pe.code_len,
                          pe.tx_per_pulse, b - n_gates, pe.exps);
@@ -249,21 +244,29 @@ window_peak(const float* __restrict__ spectra, int32_t n_gates, int32_t window_b
 
 // Peak of every gate of the learned zoom: over its window when it was zoomed,
 // over the whole full-resolution row otherwise (ties to the lowest bin, NaN
-// never wins).  When the zoom or the fallback launch split its pulses into
-// chunks, the gate's row is first summed from the chunk partials in ascending
-// chunk order and written out: [C][G][K] partials of the zoom, and for the
-// fallback the [C][k][N] partials by list slot of its adaptive chunking (C
-// from the fallback count k by the rule the fallback launch used).
+// never wins).  Workgroup b < k takes slot b of the fallback list (k = its
+// device-side count), the others the zoom list in order.  When the zoom or
+// the fallback launch split its pulses into chunks, the gate's row is first
+// summed from the chunk partials in ascending chunk order and written out:
+// [C][G][K] partials of the zoom, and for the fallback the [C][k][N] partials
+// by list slot of its adaptive chunking (C from k by the rule the fallback
+// launch used).  A few fallback gates with many chunks are the heavy items:
+// each thread keeps eight bins' loads of four chunks in flight.
 __global__ void __launch_bounds__(NT)
 split_peaks(float* __restrict__ window_spectra, const float* __restrict__ window_partial,
             int32_t zoom_chunks, float* __restrict__ full_spectra, FallbackChunks fb,
-            const int32_t* __restrict__ flag, const int32_t* __restrict__ bin_start,
-            int32_t n_gates, int32_t window_bins, int32_t fine_len, int32_t* __restrict__ peak_bin,
-            float* __restrict__ peak_power) {
+            const int32_t* __restrict__ zoom_list, const int32_t* __restrict__ fallback_list,
+            const int32_t* __restrict__ bin_start, int32_t n_gates, int32_t window_bins,
+            int32_t fine_len, int32_t* __restrict__ peak_bin, float* __restrict__ peak_power) {
   __shared__ float sv[NT / 64];
   __shared__ int sk[NT / 64];
-  const int g = blockIdx.x;
-  const bool zoomed = flag[g] != 0;
+  const int k = min(max(fb.counts[1], 0), n_gates);
+  const int b = blockIdx.x;
+  const bool zoomed = b >= k;
+  const int slot = zoomed ? b - k : b;
+  if (zoomed && slot >= min(max(fb.counts[0], 0), n_gates - k)) return;
+  const int g = zoomed ? zoom_list[slot] : fallback_list[slot];
+  if (g < 0 || g >= n_gates) return;
   const int len = zoomed ? window_bins : fine_len;
   float* row = zoomed ? window_spectra + static_cast<int64_t>(g) * window_bins
                       : full_spectra + static_cast<int64_t>(g) * fine_len;
@@ -275,33 +278,45 @@ split_peaks(float* __restrict__ window_spectra, const float* __restrict__ window
     part = window_partial + static_cast<int64_t>(g) * len;
     cstride = static_cast<int64_t>(n_gates) * len;
   } else {
-    const int k = min(max(fb.counts[1], 0), n_gates);
     chunks = adaptive_chunks(k, fb.zgroups, fb.target, fb.max_chunks, fb.rows);
-    const int slot = chunks > 1 ? fb.slot[g] : 0;
     part = fb.partial + static_cast<int64_t>(slot) * len;
     cstride = static_cast<int64_t>(k) * len;
   }
+  constexpr int U = 8;  // bins per thread and step
   float bv = -INFINITY;
   int bk = INT_MAX;
-  // four bins per thread and step, every chunk's loads issued before the sums
-  for (int i0 = threadIdx.x; i0 < len; i0 += 4 * NT) {
-    float v[4];
+  for (int i0 = threadIdx.x; i0 < len; i0 += U * NT) {
+    float v[U];
+    if (chunks > 1) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int i = i0 + u * NT;
-      if (i >= len) {
-        v[u] = -INFINITY;
-      } else if (chunks > 1) {
-        float sum = 0.f;
-        for (int c = 0; c < chunks; ++c) sum += part[c * cstride + i];
-        row[i] = sum;
-        v[u] = sum;
-      } else {
-        v[u] = row[i];
+      for (int u = 0; u < U; ++u) v[u] = 0.f;
+      int c = 0;
+      for (; c + 4 <= chunks; c += 4) {  // 4 U loads in flight, then the sums in chunk order
+        float t[4][U];
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int i = min(i0 + u * NT, len - 1);
+            t[cc][u] = part[(c + cc) * cstride + i];
+          }
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc)
+#pragma unroll
+          for (int u = 0; u < U; ++u) v[u] += t[cc][u];
       }
+      for (; c < chunks; ++c)
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] += part[c * cstride + min(i0 + u * NT, len - 1)];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (i0 + u * NT < len) row[i0 + u * NT] = v[u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = i0 + u * NT < len ? row[i0 + u * NT] : -INFINITY;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < U; ++u) {
       const int i = i0 + u * NT;
       if (i < len && better(v[u], i, bv, bk)) {
         bv = v[u];
@@ -315,13 +330,13 @@ split_peaks(float* __restrict__ window_spectra, const float* __restrict__ window
       bk = 0;
       bv = row[0];
     }
-    int64_t b = bk;
+    int64_t pb = bk;
     if (zoomed) {
       int64_t st = bin_start[g] % fine_len;
       if (st < 0) st += fine_len;
-      b = (st + bk) % fine_len;
+      pb = (st + bk) % fine_len;
     }
-    peak_bin[g] = static_cast<int32_t>(b);
+    peak_bin[g] = static_cast<int32_t>(pb);
     if (peak_power) peak_power[g] = bv;
   }
 }
@@ -341,12 +356,14 @@ hipError_t launch_select_windows(const float* logits, int32_t n_gates, int32_t f
 
 hipError_t launch_split_peaks(float* window_spectra, const float* window_partial,
                               int32_t zoom_chunks, float* full_spectra, const FallbackChunks& fb,
-                              const int32_t* flag, const int32_t* bin_start, int32_t n_gates,
-                              int32_t window_bins, int32_t fine_len, int32_t* peak_bin,
-                              float* peak_power, hipStream_t s) {
+                              const int32_t* zoom_list, const int32_t* fallback_list,
+                              const int32_t* bin_start, int32_t n_gates, int32_t window_bins,
+                              int32_t fine_len, int32_t* peak_bin, float* peak_power,
+                              hipStream_t s) {
   hipLaunchKernelGGL(split_peaks, dim3(static_cast<unsigned>(n_gates)), dim3(NT), 0, s,
-                     window_spectra, window_partial, zoom_chunks, full_spectra, fb, flag,
-                     bin_start, n_gates, window_bins, fine_len, peak_bin, peak_power);
+                     window_spectra, window_partial, zoom_chunks, full_spectra, fb, zoom_list,
+                     fallback_list, bin_start, n_gates, window_bins, fine_len, peak_bin,
+                     peak_power);
   return hipGetLastError();
 }
 
@@ -354,11 +371,11 @@ hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int
                                        int32_t window_bins, float threshold, int32_t* bin_start,
                                        float* confidence, int32_t* flag, int32_t* zoom_list,
                                        int32_t* fallback_list, int32_t* counts, int32_t* done,
-                                       int32_t* fb_slot, const PulseExpArgs& pe, hipStream_t s) {
+                                       const PulseExpArgs& pe, hipStream_t s) {
   const unsigned blocks = static_cast<unsigned>(n_gates) + static_cast<unsigned>(pe.n_pulses);
   hipLaunchKernelGGL(select_and_exponents, dim3(blocks), dim3(NT), 0, s, logits, n_gates,
                      fine_len, window_bins, threshold, bin_start, confidence, flag, zoom_list,
-                     fallback_list, counts, done, fb_slot, pe);
+                     fallback_list, counts, done, pe);
   return hipGetLastError();
 }
 

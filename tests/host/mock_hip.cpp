@@ -665,7 +665,7 @@ static int g_select_calls = 0;
 static void emulate_select(const float* logits, int32_t G, int32_t fine_len, int32_t K,
                            int32_t* bin_start, float* confidence, int32_t* flag,
                            int32_t* zoom_list, int32_t* fallback_list, int32_t* counts,
-                           int32_t* done, int32_t* fb_slot = nullptr) {
+                           int32_t* done) {
   const int pattern = g_select_calls++ % 3;
   if (G < 1) mock_fail("select launch with an empty grid");
   if (fine_len < T_NET || fine_len % T_NET != 0 || K < 1 || K > fine_len)
@@ -679,14 +679,12 @@ static void emulate_select(const float* logits, int32_t G, int32_t fine_len, int
   ok = check_range(done, 4, "select done") && ok;
   if (!ok) return;
   if (*done != 0) mock_fail("select: completion counter not zero at the start of a call");
-  if (fb_slot && !check_range(fb_slot, size_t(G) * 4, "select fallback slots")) return;
   int nz = 0;
   for (int g = 0; g < G; ++g) {
     const bool z = pattern == 0 ? (g * 7 + 3) % 5 != 0 : pattern == 1 ? g != G / 2 : true;
     flag[g] = z ? 1 : 0;
     bin_start[g] = static_cast<int32_t>((int64_t(g) * 997) % fine_len);
     if (confidence) confidence[g] = z ? 0.95f : 0.5f;
-    if (fb_slot) fb_slot[g] = z ? -1 : g - nz;
     if (z)
       zoom_list[nz++] = g;
     else
@@ -713,11 +711,11 @@ hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int
                                        int32_t window_bins, float, int32_t* bin_start,
                                        float* confidence, int32_t* flag, int32_t* zoom_list,
                                        int32_t* fallback_list, int32_t* counts, int32_t* done,
-                                       int32_t* fb_slot, const PulseExpArgs& pe, hipStream_t st) {
+                                       const PulseExpArgs& pe, hipStream_t st) {
   PulseExpArgs e = pe;
   run_on(st, [=] {
     emulate_select(logits, n_gates, fine_len, window_bins, bin_start, confidence, flag, zoom_list,
-                   fallback_list, counts, done, fb_slot);
+                   fallback_list, counts, done);
     if (e.n_pulses < 0) mock_fail("negative pulse count");
     check_pulse_exponents(e.samples, e.sample_type, e.tx, e.stride, e.lo, e.hi, e.code_len,
                           e.tx_per_pulse, e.n_pulses, e.exps);
@@ -727,38 +725,45 @@ hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int
 
 hipError_t launch_split_peaks(float* window_spectra, const float* window_partial,
                               int32_t zoom_chunks, float* full_spectra, const FallbackChunks& f,
-                              const int32_t* flag, const int32_t* bin_start, int32_t n_gates,
-                              int32_t window_bins, int32_t fine_len, int32_t* peak_bin,
-                              float* peak_power, hipStream_t st) {
+                              const int32_t* zoom_list, const int32_t* fallback_list,
+                              const int32_t* bin_start, int32_t n_gates, int32_t window_bins,
+                              int32_t fine_len, int32_t* peak_bin, float* peak_power,
+                              hipStream_t st) {
   const FallbackChunks fb = f;
   run_on(st, [=] {
     if (n_gates < 1) mock_fail("split peaks with an empty grid");
-    if (!check_range(flag, size_t(n_gates) * 4, "split flag")) return;
     if (!check_range(fb.counts, 8, "split counts")) return;
     const int k = std::min(std::max(fb.counts[1], 0), n_gates);
+    const int nz = std::min(std::max(fb.counts[0], 0), n_gates - k);
     const int fchunks = adaptive_chunks(k, fb.zgroups, fb.target, fb.max_chunks, fb.rows);
     if (fchunks > 1 && fchunks * k > fb.rows) mock_fail("split: fallback partial rows overflow");
-    for (int g = 0; g < n_gates; ++g) {
-      const bool z = flag[g] != 0;
-      const int64_t len = z ? window_bins : fine_len;
-      check_range((z ? window_spectra : full_spectra) + g * len, size_t(len) * 4, "split row");
-      if (z) {
-        if (zoom_chunks > 1)
-          for (int c = 0; c < zoom_chunks; ++c)
-            check_range(window_partial + (int64_t(c) * n_gates + g) * len, size_t(len) * 4,
-                        "split zoom partial");
-        check_range(bin_start + g, 4, "split bin_start");
-      } else if (fchunks > 1) {
-        if (!check_range(fb.slot + g, 4, "split fallback slot")) continue;
-        const int slot = fb.slot[g];
-        if (slot < 0 || slot >= k) mock_fail("split: fallback slot outside the list");
+    // workgroups 0..k-1 take the fallback list's slots, k..k+nz-1 the zoom list's
+    if (k > 0 && !check_range(fallback_list, size_t(k) * 4, "split fallback list")) return;
+    if (nz > 0 && !check_range(zoom_list, size_t(nz) * 4, "split zoom list")) return;
+    for (int i = 0; i < k; ++i) {
+      const int g = fallback_list[i];
+      if (g < 0 || g >= n_gates) continue;
+      check_range(full_spectra + int64_t(g) * fine_len, size_t(fine_len) * 4, "split full row");
+      if (fchunks > 1)
         for (int c = 0; c < fchunks; ++c)
-          check_range(fb.partial + (int64_t(c) * k + slot) * len, size_t(len) * 4,
+          check_range(fb.partial + (int64_t(c) * k + i) * fine_len, size_t(fine_len) * 4,
                       "split fallback partial");
-      }
+      check_range(peak_bin + g, 4, "split peak bin");
+      if (peak_power) check_range(peak_power + g, 4, "split peak power");
     }
-    check_range(peak_bin, size_t(n_gates) * 4, "split peak bin");
-    if (peak_power) check_range(peak_power, size_t(n_gates) * 4, "split peak power");
+    for (int i = 0; i < nz; ++i) {
+      const int g = zoom_list[i];
+      if (g < 0 || g >= n_gates) continue;
+      const int64_t len = window_bins;
+      check_range(window_spectra + g * len, size_t(len) * 4, "split window row");
+      if (zoom_chunks > 1)
+        for (int c = 0; c < zoom_chunks; ++c)
+          check_range(window_partial + (int64_t(c) * n_gates + g) * len, size_t(len) * 4,
+                      "split zoom partial");
+      check_range(bin_start + g, 4, "split bin_start");
+      check_range(peak_bin + g, 4, "split peak bin");
+      if (peak_power) check_range(peak_power + g, 4, "split peak power");
+    }
   });
   return hipSuccess;
 }
