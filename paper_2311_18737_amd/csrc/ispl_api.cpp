@@ -243,34 +243,36 @@ uint16_t round16(double v, int precision, double* value) {
   return bits;
 }
 
-// The real DFT-matrix of the zoom GEMM, split into high and low 16-bit parts,
-// in MFMA A-operand order: for row tile rt (32 rows), k-step ks (16 reduction
-// rows) and lane l, 8 values A[32 rt + l % 32][16 ks + 8 (l / 32) + i].
-// Rows 2j / 2j+1 give Re / Im of bin j, reduction rows 2n / 2n+1 take Re / Im
-// of sample n: A = [[cos, sin], [-sin, cos]] of theta = 2 pi ((j n) mod N) / N.
+// The three real matrices of the zoom GEMM in its three-multiplication
+// complex form, split into high and low 16-bit parts, in MFMA A-operand
+// order: for product pr, bin tile bt (32 bins), k-step ks (16 samples) and
+// lane l, 8 values A_pr[32 bt + l % 32][16 ks + 8 (l / 32) + i].  With
+// theta = 2 pi ((j n) mod N) / N the DFT matrix is W = cos theta - i sin theta,
+// and A_0 = Re W + Im W = cos - sin, A_1 = Re W = cos, A_2 = Im W = -sin;
+// samples n >= L give zero columns.
 void zoom_table(int n_fft, int n_bins, int code_len, int code_pad, int precision,
                 std::vector<uint16_t>& hi, std::vector<uint16_t>& lo) {
-  const int n_rt = 2 * n_bins / 32, n_ks = 2 * code_pad / 16;
-  hi.assign(static_cast<size_t>(n_rt) * n_ks * 64 * 8, 0);
+  const int n_bt = n_bins / 32, n_ks = code_pad / 16;
+  hi.assign(static_cast<size_t>(3) * n_bt * n_ks * 64 * 8, 0);
   lo.assign(hi.size(), 0);
   size_t idx = 0;
-  for (int rt = 0; rt < n_rt; ++rt)
-    for (int ks = 0; ks < n_ks; ++ks)
-      for (int l = 0; l < 64; ++l)
-        for (int i = 0; i < 8; ++i, ++idx) {
-          const int row = 32 * rt + l % 32, k = 16 * ks + 8 * (l / 32) + i;
-          const int j = row / 2, n = k / 2;
-          double v = 0.0;
-          if (n < code_len) {
-            const int64_t m = (static_cast<int64_t>(j) * n) % n_fft;
-            const double th = 2.0 * M_PI * static_cast<double>(m) / n_fft;
-            const double c = std::cos(th), sn = std::sin(th);
-            v = (row % 2 == 0) ? (k % 2 == 0 ? c : sn) : (k % 2 == 0 ? -sn : c);
+  for (int pr = 0; pr < 3; ++pr)
+    for (int bt = 0; bt < n_bt; ++bt)
+      for (int ks = 0; ks < n_ks; ++ks)
+        for (int l = 0; l < 64; ++l)
+          for (int i = 0; i < 8; ++i, ++idx) {
+            const int j = 32 * bt + l % 32, n = 16 * ks + 8 * (l / 32) + i;
+            double v = 0.0;
+            if (n < code_len) {
+              const int64_t m = (static_cast<int64_t>(j) * n) % n_fft;
+              const double th = 2.0 * M_PI * static_cast<double>(m) / n_fft;
+              const double c = std::cos(th), sn = std::sin(th);
+              v = pr == 0 ? c - sn : (pr == 1 ? c : -sn);
+            }
+            double hv, lv;
+            hi[idx] = round16(v, precision, &hv);
+            lo[idx] = round16(v - hv, precision, &lv);
           }
-          double hv, lv;
-          hi[idx] = round16(v, precision, &hv);
-          lo[idx] = round16(v - hv, precision, &lv);
-        }
 }
 
 }  // namespace
@@ -285,6 +287,8 @@ struct ispl_zoom {
   void* a_lo;
   float* partial;    // [chunks_max][G][K] when chunks_max > 1
   int32_t* col_exp;  // [max_pulses] (FP16 only)
+  uint32_t* code_bits;    // [max_pulses][code_pad / 32] sign bits of +-1 codes
+  int32_t* code_binary;   // [max_pulses]
 };
 
 namespace {
@@ -314,7 +318,7 @@ ZoomPlan zoom_plan(int32_t n_gates, int32_t n_bins, int32_t n_pulses) {
 }  // namespace
 
 static void zoom_free(ispl_zoom* z) {
-  void* bufs[] = {z->a_hi, z->a_lo, z->partial, z->col_exp};
+  void* bufs[] = {z->a_hi, z->a_lo, z->partial, z->col_exp, z->code_bits, z->code_binary};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
 }
@@ -675,7 +679,7 @@ ispl_status ispl_zoom_create(ispl_ctx* ctx, int32_t n_bins, int32_t precision,
     return fail(ISPL_ERR_INVALID_ARG, "n_bins %d: need a multiple of 128 in [128, fft_len %d]",
                 n_bins, c.fft_len);
   const int32_t code_pad = (c.code_len + 63) / 64 * 64;
-  const int64_t bytes = int64_t{8} * n_bins * code_pad;
+  const int64_t bytes = int64_t{6} * n_bins * code_pad;  // one of the two split tables
   if (bytes > (int64_t{512} << 20))
     return fail(ISPL_ERR_UNSUPPORTED, "zoom table of %lld bytes exceeds 512 MiB",
                 static_cast<long long>(bytes));
@@ -697,6 +701,11 @@ ispl_status ispl_zoom_create(ispl_ctx* ctx, int32_t n_bins, int32_t precision,
                                    static_cast<size_t>(n_bins));
   if (e == hipSuccess && precision == ISPL_ZOOM_FP16X3)
     e = hipMalloc(&z->col_exp, sizeof(int32_t) * static_cast<size_t>(c.max_pulses));
+  if (e == hipSuccess)
+    e = hipMalloc(&z->code_bits, sizeof(uint32_t) * static_cast<size_t>(c.max_pulses) *
+                                     static_cast<size_t>(code_pad / 32));
+  if (e == hipSuccess)
+    e = hipMalloc(&z->code_binary, sizeof(int32_t) * static_cast<size_t>(c.max_pulses));
   if (e != hipSuccess) {
     zoom_free(z);
     delete z;
@@ -724,8 +733,9 @@ void ispl_zoom_destroy(ispl_zoom* z) {
 }
 
 // deferred_chunks: as for integrate_impl (partial windows [C][G][K] stay in
-// the zoom's scratch).  exponents_ready: the FP16 column exponents are already
-// in the zoom's col_exp (see launch_select_and_exponents).
+// the zoom's scratch).  exponents_ready: the per-pulse pass has already
+// written the FP16 column exponents and the code sign bits into the zoom's
+// col_exp and code_bits (see launch_select_and_exponents).
 static ispl_status zoom_impl(ispl_zoom* z, const void* samples, const float* tx_code,
                              int32_t tx_per_pulse, int32_t n_pulses, const int32_t* bin_start,
                              const int32_t* gate_list, const int32_t* gate_count, float* spectra,
@@ -792,6 +802,8 @@ static ispl_status zoom_impl(ispl_zoom* z, const void* samples, const float* tx_
   a.col_tiles = zp.ct;
   a.partial = z->partial;
   a.col_exp = z->col_exp;
+  a.code_bits = z->code_bits;
+  a.code_binary = z->code_binary;
   a.row_lo = c.first_gate;
   a.row_hi = static_cast<int64_t>(c.first_gate) + static_cast<int64_t>(c.n_gates - 1) * c.gate_step +
              c.code_len;
@@ -1259,10 +1271,12 @@ ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx
                                       true, z->coarse->partial, coarse_chunks, z->coarse_spectra);
   if (e == hipSuccess) {
     ispl::PulseExpArgs pe{};
-    const bool fp16 = z->zoom->precision == ISPL_ZOOM_FP16X3 && n_pulses > 0;
     pe.samples = samples;
     pe.tx = tx_code;
-    pe.exps = z->zoom->col_exp;
+    pe.exps = z->zoom->precision == ISPL_ZOOM_FP16X3 ? z->zoom->col_exp : nullptr;
+    pe.bits = z->zoom->code_bits;
+    pe.binary = z->zoom->code_binary;
+    pe.bit_words = z->zoom->code_pad / 32;
     pe.stride = c.pulse_stride;
     pe.lo = c.first_gate;
     pe.hi = static_cast<int64_t>(c.first_gate) + static_cast<int64_t>(c.n_gates - 1) * c.gate_step +
@@ -1270,7 +1284,7 @@ ispl_status ispl_lzoom_peaks(ispl_lzoom* z, const void* samples, const float* tx
     pe.sample_type = c.sample_type;
     pe.code_len = c.code_len;
     pe.tx_per_pulse = tx_per_pulse;
-    pe.n_pulses = fp16 ? n_pulses : 0;
+    pe.n_pulses = n_pulses > 0 ? n_pulses : 0;
     e = ispl::launch_select_and_exponents(z->logits, G, c.fft_len, z->window_bins, z->threshold,
                                           z->bin_start, z->confidence, z->flag, z->zoom_list,
                                           z->fallback_list, z->counts, z->done, pe,

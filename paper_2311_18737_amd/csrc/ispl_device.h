@@ -84,4 +84,32 @@ __device__ __forceinline__ void pulse_exponent_block(const void* __restrict__ sa
   }
 }
 
+// Sign bits of pulse p's code for the zoom DFT, by one workgroup of 256
+// threads: bit b of word w of bits[p] is set when code[32 w + b] == -1 + 0i
+// (positions past L read as +1), and binary[p] = 1 when every code of the row
+// is exactly +-1 + 0i (0: the zoom then reads the row as complex codes).
+// With a code shared by all pulses only row 0 exists (p == 0 writes it).
+__device__ __forceinline__ void code_bits_block(const float* __restrict__ tx, int32_t code_len,
+                                                int32_t tx_per_pulse, int32_t words, int p,
+                                                uint32_t* __restrict__ bits,
+                                                int32_t* __restrict__ binary) {
+  if (!tx_per_pulse && p != 0) return;  // uniform over the workgroup
+  const float2* txp = reinterpret_cast<const float2*>(tx) +
+                      (tx_per_pulse ? static_cast<int64_t>(p) * code_len : 0);
+  bool ok = true;
+  for (int w = threadIdx.x; w < words; w += 256) {
+    uint32_t word = 0;
+    for (int b = 0; b < 32; ++b) {
+      const int n = 32 * w + b;
+      if (n >= code_len) break;
+      const float2 c = txp[n];
+      ok = ok && c.y == 0.f && (c.x == 1.f || c.x == -1.f);
+      word |= (c.x < 0.f ? 1u : 0u) << b;
+    }
+    bits[static_cast<int64_t>(p) * words + w] = word;
+  }
+  ok = __syncthreads_and(ok);
+  if (threadIdx.x == 0) binary[p] = ok ? 1 : 0;
+}
+
 }  // namespace ispl

@@ -147,11 +147,17 @@ struct ZoomArgs {
   int32_t col_tiles;        // CT: 1 or 2 (32 or 64 pulses per block)
   const int32_t* gate_list; // optional: only gates gate_list[i], i < *gate_count
   const int32_t* gate_count;
+  // Optional sign bits of +-1 codes (NULL: always read tx as complex codes),
+  // written by the launch's pulse pass (launch_zoom with prep) or by
+  // launch_select_and_exponents: [rows][code_pad / 32] words, bit b of word w
+  // set when code[32 w + b] == -1, and per row 1 when the whole row is +-1.
+  uint32_t* code_bits;
+  int32_t* code_binary;
 };
 
-// With exponents = false the FP16 column exponents must already be in
-// a.col_exp (launch_select_and_exponents writes them).
-hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream, bool exponents = true);
+// With prep = false the FP16 column exponents (FP16) and the code sign bits
+// (a.code_bits) must already be written (launch_select_and_exponents does).
+hipError_t launch_zoom(const ZoomArgs& a, hipStream_t stream, bool prep = true);
 
 // Window-proposal network (learned zoom).
 constexpr int NET_LEN = 1024;      // coarse bins per gate
@@ -219,11 +225,14 @@ hipError_t launch_split_peaks(float* window_spectra, const float* window_partial
 struct PulseExpArgs {
   const void* samples;
   const float* tx;
-  int32_t* exps;
+  int32_t* exps;           // NULL: no exponents (BF16 zoom)
+  uint32_t* bits;          // NULL: no code sign bits
+  int32_t* binary;
   int64_t stride, lo, hi;  // rows and the span [lo, hi) some gate reads
-  int32_t sample_type, code_len, tx_per_pulse, n_pulses;
+  int32_t sample_type, code_len, tx_per_pulse, n_pulses, bit_words;
 };
-// select_windows and, in the same launch, the pulse exponents (n_pulses = 0: none).
+// select_windows and, in the same launch, the zoom's per-pulse pass: FP16
+// exponents and code sign bits (n_pulses = 0: none).
 hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int32_t fine_len,
                                        int32_t window_bins, float threshold, int32_t* bin_start,
                                        float* confidence, int32_t* flag, int32_t* zoom_list,

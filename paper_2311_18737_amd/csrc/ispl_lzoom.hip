@@ -202,8 +202,12 @@ select_and_exponents(const float* __restrict__ logits, int32_t n_gates, int32_t 
     select_window_block(b, logits, n_gates, fine_len, window_bins, threshold, bin_start,
                         confidence, flag, zoom_list, fallback_list, counts, done);
   } else {
-    pulse_exponent_block(pe.samples, pe.sample_type, pe.tx, pe.stride, pe.lo, pe.hi, pe.code_len,
-                         pe.tx_per_pulse, b - n_gates, pe.exps);
+    if (pe.exps)
+      pulse_exponent_block(pe.samples, pe.sample_type, pe.tx, pe.stride, pe.lo, pe.hi,
+                           pe.code_len, pe.tx_per_pulse, b - n_gates, pe.exps);
+    if (pe.bits)
+      code_bits_block(pe.tx, pe.code_len, pe.tx_per_pulse, pe.bit_words, b - n_gates, pe.bits,
+                      pe.binary);
   }
 }
 

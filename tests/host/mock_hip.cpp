@@ -414,11 +414,22 @@ static void check_rows(const void* base, int64_t row_len, const std::vector<int>
 static void check_pulse_exponents(const void* samples, int st, const float* tx, int64_t stride,
                                   int64_t lo, int64_t hi, int L, int per_pulse, int P,
                                   const int32_t* exps) {
-  if (P < 1) return;
+  if (P < 1 || !exps) return;
   if (lo < 0 || hi < lo || hi > stride) mock_fail("pulse exponents: span outside the row");
   check_range(samples, size_t(int64_t(P - 1) * stride + hi) * (st == 1 ? 4 : 8), "exp samples");
   check_range(tx, size_t(per_pulse ? P : 1) * L * 8, "exp tx");
   check_range(exps, size_t(P) * 4, "exp out");
+}
+
+// Code sign bits of the zoom's pulse pass: rows x words words and one flag per row.
+static void check_code_bits(const float* tx, int L, int per_pulse, int P, int words,
+                            const uint32_t* bits, const int32_t* binary) {
+  if (P < 1 || !bits) return;
+  if (words * 32 < L) mock_fail("code bits: fewer words than codes");
+  const int rows = per_pulse ? P : 1;
+  check_range(tx, size_t(rows) * L * 8, "bits tx");
+  check_range(bits, size_t(rows) * words * 4, "code bits");
+  check_range(binary, size_t(rows) * 4, "code binary");
 }
 
 
@@ -522,9 +533,9 @@ hipError_t launch_fill_zero_rows(float* dst, int32_t g, int32_t n, const int32_t
   run_on(st, [=] { check_rows(dst, n, active_gates(list, count, g, g), "fill_zero_rows"); });
   return hipSuccess;
 }
-hipError_t launch_zoom(const ZoomArgs& a, hipStream_t st, bool exponents) {
+hipError_t launch_zoom(const ZoomArgs& a, hipStream_t st, bool prep) {
   ZoomArgs c = a;
-  run_on(st, [c, exponents] {
+  run_on(st, [c, prep] {
     if (c.n_pulses < 1) {
       mock_fail("zoom launch without pulses (an empty grid)");
       return;
@@ -534,17 +545,25 @@ hipError_t launch_zoom(const ZoomArgs& a, hipStream_t st, bool exponents) {
         c.chunks < 1 || (c.n_fft & (c.n_fft - 1)) != 0)
       mock_fail("zoom geometry");
     if (c.precision == 1) {
-      if (exponents)
+      if (prep)
         check_pulse_exponents(c.samples, c.sample_type, c.tx, c.stride, c.row_lo, c.row_hi,
                               c.code_len, c.tx_per_pulse, c.n_pulses, c.col_exp);
       check_range(c.col_exp, size_t(c.n_pulses) * 4, "zoom col_exp");
+    }
+    if (c.code_bits) {
+      if (prep)
+        check_code_bits(c.tx, c.code_len, c.tx_per_pulse, c.n_pulses, c.code_pad / 32,
+                        c.code_bits, c.code_binary);
+      const int rows = c.tx_per_pulse ? c.n_pulses : 1;
+      check_range(c.code_bits, size_t(rows) * (c.code_pad / 32) * 4, "zoom code bits");
+      check_range(c.code_binary, size_t(rows) * 4, "zoom code binary");
     }
     const std::vector<int> gs = active_gates(c.gate_list, c.gate_count, c.n_gates, c.n_gates);
     check_windows(c.samples, c.sample_type == 1 ? 4 : 8, c.stride, c.first_gate, c.gate_step,
                   c.code_len, c.n_pulses, gs, "zoom samples");
     check_range(c.tx, size_t(c.tx_per_pulse ? c.n_pulses : 1) * c.code_len * 8, "zoom tx");
     check_range(c.twiddle, size_t(c.n_fft) * 8, "zoom twiddle");
-    const size_t table = size_t(c.n_bins / 16) * (c.code_pad / 8) * 64 * 16;
+    const size_t table = size_t(3) * (c.n_bins / 32) * (c.code_pad / 16) * 64 * 16;
     check_range(c.a_hi, table, "zoom table hi");
     check_range(c.a_lo, table, "zoom table lo");
     for (int g : gs) check_range(c.bin_start + g, 4, "zoom bin_start");
@@ -719,6 +738,7 @@ hipError_t launch_select_and_exponents(const float* logits, int32_t n_gates, int
     if (e.n_pulses < 0) mock_fail("negative pulse count");
     check_pulse_exponents(e.samples, e.sample_type, e.tx, e.stride, e.lo, e.hi, e.code_len,
                           e.tx_per_pulse, e.n_pulses, e.exps);
+    check_code_bits(e.tx, e.code_len, e.tx_per_pulse, e.n_pulses, e.bit_words, e.bits, e.binary);
   });
   return hipSuccess;
 }

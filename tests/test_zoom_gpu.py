@@ -98,6 +98,12 @@ SHAPES = [
     # L not a multiple of 4 (per-sample fetches with a ragged tail), and L = 4
     (4096, 301, 3, 40, 13, 2, "ci16", True, "bpsk", 128),
     (2048, 4, 3, 5, 3, 0, "c64", True, "gauss", 128),
+    # several 64-pulse blocks per workgroup (the sign-bit path fetches the next
+    # block's first chunk ahead), a partial last block and a ragged last chunk
+    (1024, 64, 256, 300, 1, 0, "c64", True, "bpsk", 128),
+    (2048, 100, 300, 200, 2, 0, "ci16", True, "bpsk", 256),
+    # a code too long for the gate's twiddle table in LDS (global twiddles)
+    (16384, 4100, 2, 3, 25, 0, "c64", True, "phase", 128),
 ]
 
 
@@ -121,6 +127,30 @@ def test_shapes_match_oracle(ispl, shape, precision):
     assert err["max_e"] <= TOL[precision], err
     z.close()
     ctx.close()
+
+
+def test_sign_bit_and_complex_rows(ispl):
+    """+-1 codes take the sign-bit path only where every code row of a
+    workgroup's pulses is +-1: one complex chip in pulse 70 sends the second
+    pulse chunk (pulses 50..99) to the complex-code path, the first stays on
+    sign bits; both match the oracle.  (300 gates of one 256-bin tile fill
+    less than two rounds of the chip, so the plan takes two pulse chunks.)"""
+    N, L, G, P, s, K = 2048, 96, 300, 100, 2, 256
+    stride = (G - 1) * s + L
+    samples, tx = random_inputs(P, stride, L, sample_type="c64", code_kind="bpsk", seed=11)
+    tx[70, 3] = np.exp(0.3j)
+    starts = np.random.default_rng(3).integers(0, N, size=G)
+    for precision in ("fp16x3", "bf16x3"):
+        say(f"case mixed rows {precision}")
+        ctx, z, out, *_ = run_zoom(ispl, samples, tx, starts, L=L, N=N, G=G, s=s, g0=0,
+                                   stride=stride, st="c64", K=K, precision=precision)
+        ref = window_spectra(samples, tx, n_gates=G, gate_step=s, first_gate=0, fft_len=N,
+                             tx_per_pulse=True, bin_start=starts, n_bins=K)
+        err = spectra_error(out.cpu().numpy(), ref)
+        say(f"  max_e {err['max_e']:.3e}")
+        assert err["max_e"] <= TOL[precision], err
+        z.close()
+        ctx.close()
 
 
 def test_zoom_accumulate_and_empty(ispl):
