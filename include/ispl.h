@@ -177,11 +177,12 @@ ispl_status ispl_integrate_spectra_noalloc(const ispl_config* cfg, const void* s
  * Zoom DFT on the matrix cores: K bins of the N-point spectrum of every gate,
  * starting at a per-gate bin, without the full transform.  Each gate's
  * decoded rows are shifted so that its window starts at bin 0 and multiplied
- * by one K x L DFT matrix shared by all gates and pulses, on BF16 or FP16
- * MFMA with both operands split into high and low halves (three products,
- * FP32 accumulation); decode, shift and the pulse sum stay FP32.  The result
- * is the same quantity as ispl_integrate_spectra at those bins (Section 2.2,
- * Eqs. 7-8), at the precision of the chosen split.
+ * by one K x L DFT matrix shared by all gates and pulses (the complex product
+ * as three real products), on BF16 or FP16 MFMA with both operands split into
+ * high and low halves (three split products each, FP32 accumulation);
+ * decode, shift and the pulse sum stay FP32.  The result is the same
+ * quantity as ispl_integrate_spectra at those bins (Section 2.2, Eqs. 7-8),
+ * at the precision of the chosen split.
  */
 typedef enum {
   ISPL_ZOOM_BF16X3 = 0,  /* BF16 hi/lo split: ~16 significant bits per product */
@@ -191,8 +192,10 @@ typedef enum {
 typedef struct ispl_zoom ispl_zoom; /* opaque; must not outlive its context */
 
 /* Builds the split DFT-matrix table for windows of n_bins bins (a multiple of
- * 128, at most fft_len) of ctx's geometry.  Table size is 8 * n_bins *
- * round_up(code_len, 64) bytes; ISPL_ERR_UNSUPPORTED above 512 MiB. */
+ * 128, at most fft_len) of ctx's geometry: two halves of 6 * n_bins *
+ * round_up(code_len, 64) bytes each; ISPL_ERR_UNSUPPORTED above 512 MiB per
+ * half.  Also holds the per-call scratch: FP16 exponents and the sign bits of
+ * +-1 codes for max_pulses pulses. */
 ispl_status ispl_zoom_create(ispl_ctx* ctx, int32_t n_bins, int32_t precision,
                              ispl_zoom** out);
 

@@ -6,27 +6,29 @@
 //
 // i.e. the decoded row of Section 3.2 shifted so that bin k0_g (the window
 // start of gate g) sits at 0, then a direct DFT onto K bins.  The DFT matrix
-// W_N^{j n} is the same for every gate and pulse, so the work is one real
-// GEMM per gate: rows 2j, 2j+1 hold Re/Im of bin j, columns are pulses and
-// the reduction runs over (Re, Im) of the L samples.
+// W = W_N^{j n} = Wr + i Wi is the same for every gate and pulse; the complex
+// product Z = W y takes three real GEMMs per gate (rows: bins, columns:
+// pulses, reduction: the L samples), k1 = (Wr + Wi) yr, k2 = Wr (yi - yr),
+// k3 = Wi (yr + yi), with Re Z = k1 - k3 and Im Z = k1 + k2.
 //
 // Precision: both operands are split into a high and a low 16-bit part
 // (BF16 or FP16) and D = A_hi B_hi + A_hi B_lo + A_lo B_hi accumulates in
 // FP32; the dropped A_lo B_lo term and the split residuals are about 2^-16
 // (BF16) or 2^-22 (FP16) of each product.  FP16 columns (pulses) are scaled by a
 // power of two that puts the largest decoded sample of the pulse below 2^14
-// (no overflow; low parts stay normal) and the scale is removed exactly
-// before the pulse sum.  Decode,
-// shift and pulse integration run in FP32.
+// (no overflow, yr + yi stays below 2^15; low parts stay normal) and the
+// scale is removed exactly before the pulse sum.  Decode, shift and pulse
+// integration run in FP32.
 //
 // Tiling: a workgroup owns one gate, 128 or 256 bins and a chunk of the
 // pulses, which it sweeps in blocks of 32 or 64 columns (one or two 32x32
-// tiles).  Eight matrix waves hold one or two 32-row MFMA tiles each; four
+// tiles).  Eight matrix waves hold k1, k2, k3 of one 32-bin tile each; four
 // building waves decode, shift and split the samples of the next 64-sample
 // chunk into LDS, in the MFMA B-operand layout, while the matrix waves
-// multiply the current one (double buffer).  The A operand (DFT matrix,
-// split) streams from a table laid out in the A-operand order, 16 bytes per
-// lane per k-step, two k-steps ahead.  Pulse chunks of one gate write
+// multiply the current one (double buffer).  The A operands (the three split
+// matrices) stream from a table laid out in the A-operand order, 16 bytes per
+// lane per k-step and product, one k-step ahead.  +-1 codes are read as sign
+// bits, the gate's shift twiddles from LDS.  Pulse chunks of one gate write
 // partial windows that a fixed-order pass sums.
 
 #include <hip/hip_runtime.h>
