@@ -88,6 +88,7 @@ __device__ __forceinline__ void pulse_exponent_block(const void* __restrict__ sa
 // threads: bit b of word w of bits[p] is set when code[32 w + b] == -1 + 0i
 // (positions past L read as +1), and binary[p] = 1 when every code of the row
 // is exactly +-1 + 0i (0: the zoom then reads the row as complex codes).
+// words * 32 must be a multiple of 64 (one ballot of a wave gives two words).
 // With a code shared by all pulses only row 0 exists (p == 0 writes it).
 __device__ __forceinline__ void code_bits_block(const float* __restrict__ tx, int32_t code_len,
                                                 int32_t tx_per_pulse, int32_t words, int p,
@@ -96,17 +97,22 @@ __device__ __forceinline__ void code_bits_block(const float* __restrict__ tx, in
   if (!tx_per_pulse && p != 0) return;  // uniform over the workgroup
   const float2* txp = reinterpret_cast<const float2*>(tx) +
                       (tx_per_pulse ? static_cast<int64_t>(p) * code_len : 0);
+  const int lane = threadIdx.x & 63;
   bool ok = true;
-  for (int w = threadIdx.x; w < words; w += 256) {
-    uint32_t word = 0;
-    for (int b = 0; b < 32; ++b) {
-      const int n = 32 * w + b;
-      if (n >= code_len) break;
+  for (int n0 = 64 * (threadIdx.x >> 6); n0 < 32 * words; n0 += 256) {  // wave-uniform
+    const int n = n0 + lane;
+    bool neg = false;
+    if (n < code_len) {
       const float2 c = txp[n];
       ok = ok && c.y == 0.f && (c.x == 1.f || c.x == -1.f);
-      word |= (c.x < 0.f ? 1u : 0u) << b;
+      neg = c.x < 0.f;
     }
-    bits[static_cast<int64_t>(p) * words + w] = word;
+    const uint64_t m = __ballot(neg);
+    if (lane == 0) {
+      uint32_t* w = bits + static_cast<int64_t>(p) * words + n0 / 32;
+      w[0] = static_cast<uint32_t>(m);
+      w[1] = static_cast<uint32_t>(m >> 32);
+    }
   }
   ok = __syncthreads_and(ok);
   if (threadIdx.x == 0) binary[p] = ok ? 1 : 0;
