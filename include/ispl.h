@@ -27,7 +27,11 @@
  *     nothing is launched and no output is written; the call returns a
  *     non-zero ispl_status and ispl_last_error() describes the problem.
  *   - Nothing throws or aborts across this ABI.
- *   - A context is not thread-safe: one thread at a time per context.
+ *   - A context is not thread-safe: one thread at a time per context.  A
+ *     context and the objects built on it (zoom, learned zoom) own scratch
+ *     (pulse-chunk partials, FP16 exponents, code sign bits) that every call
+ *     reuses, so calls on one context or object must not overlap on
+ *     different streams either.
  *   - Results are bit-identical from run to run for the same context,
  *     arguments and device (no atomics, fixed reduction order).
  */
