@@ -102,7 +102,9 @@ SHAPES = [
     # block's first chunk ahead), a partial last block and a ragged last chunk
     (1024, 64, 256, 300, 1, 0, "c64", True, "bpsk", 128),
     (2048, 100, 300, 200, 2, 0, "ci16", True, "bpsk", 256),
-    # a code too long for the gate's twiddle table in LDS (global twiddles)
+    # the longest code whose twiddles are staged in LDS (sign bits), and one
+    # too long for that table (global twiddles)
+    (16384, 4096, 2, 3, 25, 0, "ci16", True, "bpsk", 640),
     (16384, 4100, 2, 3, 25, 0, "c64", True, "phase", 128),
 ]
 
