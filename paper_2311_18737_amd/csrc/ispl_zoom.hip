@@ -216,8 +216,9 @@ __device__ __forceinline__ float2 shift_twiddle(const float2* tws, const float2*
   return tw[(k0 * static_cast<uint32_t>(ne)) & nmask];
 }
 
-// The item's 8 samples of chunk ch (VEC: L % 4 == 0, so each half group lies
-// wholly inside [0, L) or wholly past it and is one 16- or 32-byte access).
+// The item's 8 samples from sample nb on (VEC: L % 4 == 0, so each half group
+// lies wholly inside [0, L) or wholly past it and is one 16- or 32-byte
+// access).
 template <int ST, bool VEC>
 __device__ __forceinline__ void fetch_samples(const ZoomArgs& a, typename RawSample<ST>::type (&x)[8],
                                               const Item& it, int nb) {
@@ -476,7 +477,7 @@ __global__ void __launch_bounds__(ZTA) zoom_spectra(ZoomArgs a) {
     // chunk barrier
     __builtin_amdgcn_s_setprio(2);
     const int bt_id = tid - 64 * ZW;
-    const int q = bt_id & 3, pc = bt_id >> 2;  // one item per thread and chunk
+    const int q = bt_id & 3, pc = bt_id >> 2;  // one item per thread and half chunk
     static_assert(64 * ZP / 4 == 64, "items cover two column tiles");
     if (tw_lds) {  // the gate's shift twiddles, once
       const float2* __restrict__ tw = reinterpret_cast<const float2*>(a.twiddle);
