@@ -131,6 +131,54 @@ def test_shapes_match_oracle(ispl, shape, precision):
     ctx.close()
 
 
+def draw_random_shapes(seed=18737, n=16):
+    """Seeded random geometries (the same on every run) in the SHAPES format,
+    each with its precision and a seed for its inputs and window starts;
+    pulses x gates x N stays below 4e7."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        N = int(rng.choice([1024, 2048, 4096, 8192, 16384, 32768, 65536]))
+        L = int(rng.integers(1, 1025)) if N < 16384 or rng.random() < 0.6 else \
+            int(rng.integers(1025, 6001))
+        K = 128 * int(rng.integers(1, min(N, 1024) // 128 + 1))
+        G = int(rng.integers(1, 60))
+        P = int(rng.integers(1, 150))
+        while P * G * N > 4e7 and G > 1:  # keeps the oracle near a second per case
+            G = max(1, G // 2)
+        while P * G * N > 4e7 and P > 1:
+            P = max(1, P // 2)
+        s = int(rng.integers(1, 50))
+        g0 = int(rng.integers(0, 6))
+        st = str(rng.choice(["c64", "ci16"]))
+        kind = str(rng.choice(["bpsk", "phase", "gauss"]))
+        per_pulse = bool(rng.integers(0, 2))
+        prec = str(rng.choice(["fp16x3", "bf16x3"]))
+        out.append((N, L, G, P, s, g0, st, per_pulse, kind, K, prec, int(rng.integers(0, 2**31))))
+    return out
+
+
+@pytest.mark.parametrize("case", draw_random_shapes(),
+                         ids=lambda t: "N{}_L{}_G{}_P{}_K{}_{}".format(*t[:4], t[9], t[10]))
+def test_random_shapes_match_oracle(ispl, case):
+    N, L, G, P, s, g0, st, per_pulse, kind, K, precision, seed = case
+    say(f"case {case}")
+    stride = g0 + (G - 1) * s + L + seed % 5
+    samples, tx = random_inputs(P, stride, L, sample_type=st, code_kind=kind,
+                                tx_rows=None if per_pulse else 1, seed=seed,
+                                amplitude=3000.0 if st == "ci16" else 1.0)
+    starts = np.random.default_rng(seed).integers(-2 * N, 2 * N, size=G)
+    ctx, z, out, *_ = run_zoom(ispl, samples, tx, starts, L=L, N=N, G=G, s=s, g0=g0,
+                               stride=stride, st=st, K=K, precision=precision)
+    ref = window_spectra(samples, tx, n_gates=G, gate_step=s, first_gate=g0, fft_len=N,
+                         tx_per_pulse=per_pulse, bin_start=starts, n_bins=K)
+    err = spectra_error(out.cpu().numpy(), ref)
+    say(f"  max_e {err['max_e']:.3e}")
+    assert err["max_e"] <= TOL[precision], err
+    z.close()
+    ctx.close()
+
+
 def test_sign_bit_and_complex_rows(ispl):
     """+-1 codes take the sign-bit path only where every code row of a
     workgroup's pulses is +-1: one complex chip in pulse 70 sends the second
