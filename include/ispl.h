@@ -51,7 +51,7 @@ typedef struct ispl_ctx ispl_ctx; /* opaque, owned by the library */
 typedef enum {
   ISPL_OK = 0,
   ISPL_ERR_INVALID_ARG = 1,  /* bad pointer, size or layout */
-  ISPL_ERR_UNSUPPORTED = 2,  /* valid, but outside what this build implements */
+  ISPL_ERR_UNSUPPORTED = 2,  /* valid, but outside what this library implements */
   ISPL_ERR_OUT_OF_MEMORY = 3,
   ISPL_ERR_DEVICE = 4        /* no usable gfx950 device, or a HIP runtime error */
 } ispl_status;
@@ -69,7 +69,7 @@ typedef enum {
 typedef struct {
   int32_t abi_version;  /* must be ISPL_ABI_VERSION */
   int32_t code_len;     /* L >= 1: transmit code length in samples */
-  int32_t fft_len;      /* N: power of two, L <= N.  This build: 1024 <= N <= 65536
+  int32_t fft_len;      /* N: power of two, L <= N.  This library: 1024 <= N <= 65536
                            with L <= 1024, or 16384 <= N <= 65536 with
                            L <= 16384 (other valid shapes: ISPL_ERR_UNSUPPORTED) */
   int32_t n_gates;      /* G >= 1 range gates */

@@ -162,7 +162,7 @@ ispl_status validate_config(const ispl_config* c) {
     return fail(ISPL_ERR_INVALID_ARG,
                 "pulse_stride %lld < first_gate + (n_gates-1)*gate_step + code_len = %lld",
                 static_cast<long long>(c->pulse_stride), static_cast<long long>(need));
-  // what this build implements
+  // what this library implements
   if (c->fft_len < ispl::SUB || c->fft_len > 65536)
     return fail(ISPL_ERR_UNSUPPORTED, "fft_len %d outside [1024, 65536]", c->fft_len);
   if (c->code_len > 16 * ispl::SUB)

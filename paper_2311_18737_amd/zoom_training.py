@@ -210,7 +210,7 @@ def evaluate(params, n_sets: int = 16, threshold: float = 0.9, window_bins: int 
              seed0: int = EVAL_SEED0, log=None):
     """Learned zoom on held-out datasets against the full-resolution peaks.
 
-    Returns per-gate arrays: full-FFT peak (the judge), learned-zoom peak,
+    Returns per-gate arrays: full-FFT peak (the reference), learned-zoom peak,
     whether the gate was zoomed, its confidence, and the coarse-argmax
     heuristic's peak (window on the coarse spectrum's argmax, always zoomed).
     """
@@ -232,12 +232,12 @@ def evaluate(params, n_sets: int = 16, threshold: float = 0.9, window_bins: int 
     hz = Zoom(maker.fine, window_bins, "fp16x3")
     all_gates = torch.arange(cfg.n_gates, dtype=torch.int32, device=maker.dev)
     count = torch.tensor([cfg.n_gates], dtype=torch.int32, device=maker.dev)
-    out = {k: [] for k in ("judge", "learned", "zoomed", "confidence", "heuristic", "snr_db",
+    out = {k: [] for k in ("full_fft", "learned", "zoomed", "confidence", "heuristic", "snr_db",
                            "truth")}
     for i in range(n_sets):
         d = make_dataset(cfg, seed0 + i, cache_dir=None)
         xs, xt = maker.upload(d.samples, d.tx)
-        judge, _ = maker.fine_peaks(xs, xt)
+        full_fft, _ = maker.fine_peaks(xs, xt)
         bins, _ = lz.peaks(xs, xt)
         torch.cuda.synchronize()
         v = lz.view()
@@ -252,7 +252,7 @@ def evaluate(params, n_sets: int = 16, threshold: float = 0.9, window_bins: int 
         hstart = ((m * maker.S - window_bins // 2) % cfg.fft_len).to(torch.int32)
         hs = hz.spectra(xs, xt, hstart)
         hb, _ = hz.find_peaks(hs, hstart, (all_gates, count))
-        out["judge"].append(judge.cpu().numpy())
+        out["full_fft"].append(full_fft.cpu().numpy())
         out["learned"].append(bins.cpu().numpy())
         out["zoomed"].append(zoomed)
         out["confidence"].append(conf)
@@ -273,8 +273,8 @@ def summarise(ev: dict, fine_len: int = 16384) -> dict:
         d = np.mod(a.astype(np.int64) - b.astype(np.int64), fine_len)
         return np.minimum(d, fine_len - d)
 
-    e_learn = err(ev["learned"], ev["judge"])
-    e_heur = err(ev["heuristic"], ev["judge"])
+    e_learn = err(ev["learned"], ev["full_fft"])
+    e_heur = err(ev["heuristic"], ev["full_fft"])
     z = ev["zoomed"]
     # the heuristic restricted to the gates the network zooms (same split)
     return {

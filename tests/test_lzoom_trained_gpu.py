@@ -1,4 +1,4 @@
-"""The trained learned zoom on held-out data, judged by the full-FFT path.
+"""The trained learned zoom on held-out data, checked against the full-FFT path.
 
 Target: the learned peak lies within one full-resolution bin of the full-FFT
 peak on at least 99 % of gates.  Ablation: the same zoom with the window put
@@ -41,18 +41,18 @@ def bin_err(a, b, n=16384):
 
 
 def test_learned_zoom_meets_the_one_bin_target(ev):
-    e = bin_err(ev["learned"], ev["judge"])
+    e = bin_err(ev["learned"], ev["full_fft"])
     assert ev["learned"].size == 2048
     assert np.mean(e <= 1) >= 0.99
-    # fallback gates carry the judge's own peak
-    assert np.array_equal(ev["learned"][~ev["zoomed"]], ev["judge"][~ev["zoomed"]])
+    # fallback gates carry the full-FFT path's own peak
+    assert np.array_equal(ev["learned"][~ev["zoomed"]], ev["full_fft"][~ev["zoomed"]])
     assert ev["zoomed"].mean() >= 0.5  # the zoom does the work on most gates
 
 
 def test_network_gains_over_the_coarse_argmax(ev):
     z = ev["zoomed"]
-    e_l = bin_err(ev["learned"], ev["judge"])
-    e_h = bin_err(ev["heuristic"], ev["judge"])
+    e_l = bin_err(ev["learned"], ev["full_fft"])
+    e_h = bin_err(ev["heuristic"], ev["full_fft"])
     acc_l, acc_h = np.mean(e_l <= 1), np.mean(e_h <= 1)
     assert acc_l >= acc_h
     assert (~z).any()
@@ -62,8 +62,8 @@ def test_network_gains_over_the_coarse_argmax(ev):
     assert np.corrcoef(ev["confidence"], ev["snr_db"])[0, 1] > 0.1
 
 
-def test_judge_agrees_with_the_oracle_on_one_dataset():
-    """The GPU full-FFT judge against the FP64 oracle's peaks (one held-out
+def test_full_fft_peaks_agree_with_the_oracle_on_one_dataset():
+    """The GPU full-FFT peaks against the FP64 oracle's peaks (one held-out
     dataset, all 64 gates)."""
     ensure_library()
     from paper_2311_18737_amd import zoom_training as zt

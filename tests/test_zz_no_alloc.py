@@ -106,7 +106,7 @@ def test_no_alloc_rejects_bad_arguments(ispl):
     out = torch.zeros((cfg.n_gates, cfg.fft_len), dtype=torch.float32, device=DEV)
     with pytest.raises(IsplError):  # more pulses than max_pulses
         ispl.integrate_spectra_noalloc(xs, xt, out, max_pulses=3, **geo)
-    with pytest.raises(IsplError):  # FFT length beyond this build
+    with pytest.raises(IsplError):  # FFT length beyond this library
         bad = dict(geo, fft_len=131072)
         ispl.integrate_spectra_noalloc(xs, xt, torch.zeros((cfg.n_gates, 131072), device=DEV),
                                        **bad)
