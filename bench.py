@@ -172,7 +172,8 @@ def paper_workload(steps: int, seed: int, dev):
     units = cfg.n_pulses * cfg.n_gates
     log(f"paper workload: {wall * 1e3:.3f} ms per run, integrate {integ:.3f} ms")
     ctx.close()
-    host = streaming_time(d, cfg, dev, slot_pulses=25)
+    # copying a pulse's gate span takes about a fifth of its integration time
+    host = streaming_time(d, cfg, dev, ramp_batches(cfg.n_pulses, 5, 4))
     log(f"paper workload from pinned host memory: {host}")
     return {
         "workload": "paper Section 4 shape: 100 pulses x 4096 gates, code length 16384, "
@@ -326,35 +327,48 @@ def zoom_study(steps: int, seed: int, dev):
     return out
 
 
-def streaming_time(d, cfg, dev, slot_pulses: int, reps: int = 3):
+def ramp_batches(n_pulses: int, first: int, factor: int):
+    """Batch sizes first, factor x first, factor^2 x first, ... (the last batch
+    takes the remainder).  While one batch integrates, the next is copied; with
+    `factor` at most the ratio of integration time to copy time per pulse, every
+    copy but the small first one is hidden, and the job takes few launches."""
+    sizes, n = [], max(1, first)
+    while sum(sizes) < n_pulses:
+        sizes.append(min(n, n_pulses - sum(sizes)))
+        n *= factor
+    return sizes
+
+
+def streaming_time(d, cfg, dev, batches, reps: int = 3):
     """Whole-job time with the rows starting in pinned host memory (the paper's
-    timing scope): every slot of the ring is filled once, then all pulses are
-    submitted (copy of only the gate span, overlapped with integration) and
-    the stream is synchronised.  Median over `reps` runs."""
+    timing scope): each batch of `batches` (pulse counts, in order) has a slot
+    of the ring and is filled once, then all batches are submitted (copy of
+    only the gate span, overlapped with integration) and the stream is
+    synchronised.  Median over `reps` runs."""
     import numpy as np
     import torch
 
     import paper_2311_18737_amd as ispl
 
     P = cfg.n_pulses
-    n_slots = -(-P // slot_pulses)
+    assert sum(batches) == P and min(batches) >= 1
+    n_slots = len(batches)
+    first = np.concatenate([[0], np.cumsum(batches)[:-1]]).astype(int)
     ing = ispl.StreamIngest(code_len=cfg.code_len, fft_len=cfg.fft_len, n_gates=cfg.n_gates,
                             gate_step=cfg.gate_step, first_gate=cfg.first_gate,
                             pulse_stride=cfg.pulse_stride, sample_type=cfg.sample_type,
-                            slot_pulses=slot_pulses, n_slots=max(2, n_slots))
-    for k in range(n_slots):
-        n = min(slot_pulses, P - k * slot_pulses)
+                            slot_pulses=max(batches), n_slots=max(2, n_slots))
+    for k, (p0, n) in enumerate(zip(first, batches)):
         hs, hc = ing.slot(k)
-        hs[:n] = d.samples[k * slot_pulses:k * slot_pulses + n]
-        hc[:n] = d.tx[k * slot_pulses:k * slot_pulses + n]
+        hs[:n] = d.samples[p0:p0 + n]
+        hc[:n] = d.tx[p0:p0 + n]
     out = torch.empty((cfg.n_gates, cfg.fft_len), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
     times = []
     for _ in range(reps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(n_slots):
-            n = min(slot_pulses, P - k * slot_pulses)
+        for k, n in enumerate(batches):
             ing.submit(k, n, out, accumulate=k > 0, stream=stream)
         ing.sync()
         torch.cuda.synchronize()
@@ -364,7 +378,7 @@ def streaming_time(d, cfg, dev, slot_pulses: int, reps: int = 3):
     need = (cfg.n_gates - 1) * cfg.gate_step + cfg.code_len
     h2d = P * (need * bps + cfg.code_len * 8)
     t = float(np.median(times[1:]))
-    return {"ms": t * 1e3, "slot_pulses": slot_pulses, "h2d_bytes": h2d,
+    return {"ms": t * 1e3, "batches": list(map(int, batches)), "h2d_bytes": h2d,
             "h2d_GBs_sustained": h2d / t / 1e9, "spectra_per_s": P * cfg.n_gates / t,
             "realtime_factor": P * 10e-3 / t}
 
@@ -676,7 +690,8 @@ def main():
 
     streaming = None
     if args.stream_reps > 0:
-        streaming = streaming_time(d, cfg, dev, slot_pulses=100, reps=args.stream_reps)
+        streaming = streaming_time(d, cfg, dev, ramp_batches(cfg.n_pulses, 16, 4),
+                                   reps=args.stream_reps)
         streaming["device_resident_ms"] = ms_per_step
         log(f"streaming ingest: {streaming}")
 
