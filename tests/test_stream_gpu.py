@@ -78,6 +78,51 @@ def test_stream_equals_batchwise_integration(ispl, st, N, L, G, P, batch, g0, pe
     ing.close()
 
 
+@pytest.mark.parametrize("st,N,L,G,batches", [
+    ("ci16", 16384, 1000, 5, [3, 12, 25, 20]),   # growing batches, slots reused
+    ("c64", 16384, 16384, 2, [2, 8, 30]),        # the paper's code length
+])
+def test_stream_growing_batches(ispl, st, N, L, G, batches):
+    """Batches of different sizes (the schedule the benchmark streams with)
+    through a two-slot ring: each slot's copy waits for the integration that
+    last read it; the result equals batch-by-batch integration bit for bit."""
+    print(f"case {st} N={N} L={L} G={G} batches={batches}", flush=True)
+    sys.stdout.flush()
+    s, g0 = 25, 3
+    P = sum(batches)
+    stride = g0 + (G - 1) * s + L + 5
+    samples, tx = random_inputs(P, stride, L, sample_type=st, code_kind="bpsk",
+                                seed=N + L + P, amplitude=3000.0 if st == "ci16" else 1.0)
+    ing = ispl.StreamIngest(code_len=L, fft_len=N, n_gates=G, gate_step=s, first_gate=g0,
+                            pulse_stride=stride, sample_type=st, slot_pulses=max(batches),
+                            n_slots=2)
+    ctx = ispl.Context(code_len=L, fft_len=N, n_gates=G, gate_step=s, first_gate=g0,
+                       pulse_stride=stride, sample_type=st, max_pulses=max(batches))
+    xs = torch.from_numpy(np.ascontiguousarray(samples)).to(DEV)
+    xt = torch.from_numpy(np.ascontiguousarray(tx)).to(DEV)
+    out = torch.empty((G, N), dtype=torch.float32, device=DEV)
+    ref = torch.empty((G, N), dtype=torch.float32, device=DEV)
+    p0 = 0
+    for k, n in enumerate(batches):
+        slot = k % 2
+        ing.wait_slot(slot)
+        hs, hc = ing.slot(slot)
+        hs[:n] = samples[p0:p0 + n]
+        hc[:n] = tx[p0:p0 + n]
+        ing.submit(slot, n, out, accumulate=k > 0)
+        ctx.integrate_spectra(xs[p0:p0 + n], xt[p0:p0 + n], out=ref, accumulate=k > 0)
+        p0 += n
+    ing.sync()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    want = integrate_spectra(samples, tx, n_gates=G, gate_step=s, first_gate=g0, fft_len=N,
+                             tx_per_pulse=True)
+    err = spectra_error(out.cpu().numpy(), want)
+    assert err["max_e"] <= 1e-5, err
+    ctx.close()
+    ing.close()
+
+
 def test_stream_slot_rules(ispl):
     ing = ispl.StreamIngest(code_len=64, fft_len=1024, n_gates=2, gate_step=10,
                             slot_pulses=4, n_slots=2)
