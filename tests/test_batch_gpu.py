@@ -228,3 +228,43 @@ def test_tile_shape_beyond_scratch_and_an_error_inside_capture(ispl):
         for o, r in zip(outs, ref):
             assert torch.equal(o, r), use_graph
     b.close()
+
+
+def random_modes(seed, n_modes):
+    """Seeded random modes (L, N, G, P) that the build supports."""
+    rng = np.random.default_rng(seed)
+    modes = []
+    for _ in range(n_modes):
+        N = int(2 ** rng.integers(10, 16))
+        L = int(rng.integers(1, 1025)) if N < 16384 or rng.random() < 0.5 else \
+            int(rng.integers(1025, min(N, 16384) + 1))
+        G = int(rng.integers(1, 40))
+        P = int(rng.integers(1, 24))
+        while P * G * N > 1.5e7 and G > 1:
+            G //= 2
+        modes.append((L, N, G, P))
+    return modes
+
+
+@pytest.mark.parametrize("seed,n_modes,st", [(31, 2, "c64"), (32, 5, "ci16"), (33, 3, "c64"),
+                                             (34, 4, "ci16")])
+def test_random_modes_equal_each_mode_and_the_oracle(ispl, seed, n_modes, st):
+    modes = random_modes(seed, n_modes)
+    say(f"case seed {seed} {st}: modes {modes}")
+    geo, data = make(modes, st, seed=seed)
+    inputs = [(torch.from_numpy(x).to(DEV), torch.from_numpy(t).to(DEV)) for x, t in data]
+    ref = per_mode(ispl, geo, data, st)
+    b = ispl.Batch(geo, sample_type=st)
+    for use_graph in (True, False):
+        outs = [torch.full_like(r, -1.0) for r in ref]
+        b.integrate(inputs, outs, use_graph=use_graph)
+        torch.cuda.synchronize()
+        for m, (o, r) in enumerate(zip(outs, ref)):
+            assert torch.equal(o, r), (m, use_graph)
+    for g, (samples, tx), r in zip(geo, data, ref):
+        want = integrate_spectra(samples, tx, n_gates=g["n_gates"], gate_step=g["gate_step"],
+                                 first_gate=g["first_gate"], fft_len=g["fft_len"],
+                                 tx_per_pulse=True)
+        err = spectra_error(r.cpu().numpy(), want)
+        assert err["max_e"] <= 1e-5, (g, err)
+    b.close()
