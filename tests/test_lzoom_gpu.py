@@ -334,3 +334,80 @@ def test_learned_zoom_without_pulses(ispl):
     lz.close()
     fresh.close()
     net.close()
+
+
+def random_lzoom_cases(seed=2311, n=5):
+    """Seeded random learned-zoom geometries: (N, K, L, G, P, sample type, quantile)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        N = int(2 ** rng.integers(11, 17))          # 2048 .. 65536
+        lo = 2 * N // 1024 // 128 + 1                # K > 2 N / 1024, a multiple of 128
+        K = 128 * int(rng.integers(lo, min(N, 1024) // 128 + 1))
+        L = int(rng.integers(1, 1025))
+        G = int(rng.integers(8, 70))
+        P = int(rng.integers(2, 40))
+        while P * G * N > 2.5e7 and P > 2:
+            P //= 2
+        st = str(rng.choice(["c64", "ci16"]))
+        q = float(rng.choice([0.1, 0.3, 0.6]))
+        out.append((N, K, L, G, P, st, q, int(rng.integers(0, 2 ** 31))))
+    return out
+
+
+@pytest.mark.parametrize("case", random_lzoom_cases(),
+                         ids=lambda t: "N{}_K{}_L{}_G{}_P{}_{}".format(*t[:6]))
+def test_random_learned_zoom_matches_building_blocks_and_oracle(ispl, case):
+    """Seeded random geometries, random network weights and a threshold at a
+    quantile of the confidences (so both branches are taken): the composed
+    learned zoom equals the building blocks chained by hand on the zoomed
+    gates, and every gate's peak equals the oracle's up to certified
+    near-ties."""
+    N, K, L, G, P, st, q, seed = case
+    say(f"case {case}")
+    s = 17
+    stride = (G - 1) * s + L + 3
+    samples, tx = random_inputs(P, stride, L, sample_type=st, code_kind="bpsk", seed=seed,
+                                amplitude=3000.0 if st == "ci16" else 1.0)
+    net = ispl.Net(1)
+    net.set_params(cnn.init_params(seed % 1000).astype(np.float32))
+    geo = dict(code_len=L, n_gates=G, gate_step=s, pulse_stride=stride, max_pulses=P,
+               sample_type=st)
+    coarse = ispl.Context(fft_len=1024, **geo)
+    fine = ispl.Context(fft_len=N, **geo)
+    xs, xt = dev(samples), dev(tx)
+    logits = net.forward(net.features(coarse.integrate_spectra(xs, xt)), precision="bf16")
+    conf = net.select(logits, N, K, 0.5)["confidence"].cpu().numpy()
+    thr = float(np.quantile(conf, q))
+    lz = ispl.LearnedZoom(net, window_bins=K, fft_len=N, threshold=thr, **geo)
+    bins, _ = lz.peaks(xs, xt)
+    torch.cuda.synchronize()
+    v = lz.view()
+    sel = net.select(net.forward(net.features(v["coarse_spectra"].clone()), precision="bf16"),
+                     N, K, thr)
+    torch.cuda.synchronize()
+    assert torch.equal(v["counts"], sel["counts"]) and torch.equal(v["bin_start"], sel["bin_start"])
+    flag = sel["flag"].cpu().numpy().astype(bool)
+    n_zoom, n_fb = sel["counts"].cpu().numpy()
+    say(f"  threshold {thr:.4f}: zoomed {n_zoom}, fallback {n_fb}")
+    # zoomed gates: the zoom building block on the same selection, bit for bit
+    zoom = ispl.Zoom(fine, K, "fp16x3")
+    gz = (sel["zoom_list"], sel["counts"][0:1])
+    win = zoom.spectra(xs, xt, sel["bin_start"], gates=gz)
+    hb = torch.full((G,), -1, dtype=torch.int32, device=DEV)
+    zoom.find_peaks(win, sel["bin_start"], gz, out_bins=hb)
+    torch.cuda.synchronize()
+    fl = torch.from_numpy(flag).to(DEV)
+    assert torch.equal(bins[fl], hb[fl])
+    # every gate against the oracle
+    starts = sel["bin_start"].cpu().numpy().astype(np.int64)
+    ref_full = integrate_spectra(samples, tx, n_gates=G, gate_step=s, first_gate=0, fft_len=N,
+                                 tx_per_pulse=True)
+    ref_win = np.stack([ref_full[g, (starts[g] + np.arange(K)) % N] for g in range(G)])
+    want = lzo.learned_peaks(ref_win, starts, flag, ref_full)
+    near_tie_or_equal(bins.cpu().numpy(), want, ref_full, range(G), "oracle")
+    zoom.close()
+    lz.close()
+    coarse.close()
+    fine.close()
+    net.close()
