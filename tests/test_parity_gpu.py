@@ -4,9 +4,10 @@ Element-by-element comparison of full spectra on shapes that span several
 tiles and ragged tails (every FFT length the build supports, code lengths
 that are not multiples of 64, one gate, one pulse, overlapping windows),
 the small named workload in full, and the headline workload at full size in
-the launch configuration the benchmark times, compared on sampled gates and
-through Parseval's identity on every gate.  The tolerance rules are in
-parity_util.
+the launch configuration the benchmark times, compared on sampled gates,
+through Parseval's identity on every gate, and then gate by gate against the
+oracle in worker processes on the host cores (oracle_pool).  The tolerance
+rules are in parity_util.
 """
 
 import sys
@@ -20,6 +21,7 @@ from oracle import find_plasma_line as oracle_peak  # noqa: E402
 from oracle import integrate_spectra as oracle_spectra  # noqa: E402
 from synth import CONFIGS, make_dataset, random_inputs  # noqa: E402
 from tests.conftest import ensure_library  # noqa: E402
+from tests.oracle_pool import every_gate  # noqa: E402
 from tests.parity_util import assert_spectra_match, check_peaks, spectra_error  # noqa: E402
 
 pytestmark = pytest.mark.gpu
@@ -285,8 +287,9 @@ def test_bad_arguments_leave_outputs_untouched(ispl):
 def test_realistic_workload_full_size(ispl):
     """Headline workload (1000 pulses x 1000 gates, L 1000, N 16384, int16) in
     the benchmark's launch configuration: 32 sampled gates against the oracle
-    element by element, Parseval on every gate, and the line found on nearly
-    every gate."""
+    element by element, Parseval on every gate, the line found on nearly every
+    gate, and then every gate's spectrum and peak against the oracle (worker
+    processes on the host cores)."""
     cfg = CONFIGS["realistic"]
     say("case realistic workload: drawing 1000 pulses")
     d = make_dataset(cfg, 0)
@@ -323,12 +326,17 @@ def test_realistic_workload_full_size(ispl):
     say(f"  line within 2 bins of truth on {np.mean(off <= 2):.4f} of gates")
     assert np.mean(off <= 2) >= 0.95
     ctx.close()
+    say("  oracle on every gate")
+    n, max_e, near = every_gate(d.samples, d.tx, S, bins, n_gates=G, gate_step=s, first_gate=0,
+                                fft_len=N, tx_per_pulse=True)
+    say(f"  every gate: {n} gates, max e {max_e:.3e}, certified near-ties {near}")
+    assert n == G
 
 
 def test_paper_workload_full_size(ispl):
     """The paper's own Section 4 shape (100 pulses x 4096 gates, L = N = 16384,
-    gate step 25): 16 sampled gates against the oracle and Parseval on all
-    gates."""
+    gate step 25): 16 sampled gates against the oracle, Parseval on all gates,
+    then every gate's spectrum and peak against the oracle."""
     cfg = CONFIGS["paper"]
     say("case paper workload: drawing 100 pulses")
     d = make_dataset(cfg, 0)
@@ -356,3 +364,8 @@ def test_paper_workload_full_size(ispl):
     say(f"  Parseval max rel {rel.max():.3e}")
     assert rel.max() < 1e-5
     ctx.close()
+    say("  oracle on every gate")
+    n, max_e, near = every_gate(d.samples, d.tx, S, bins, n_gates=G, gate_step=s, first_gate=0,
+                                fft_len=N, tx_per_pulse=True)
+    say(f"  every gate: {n} gates, max e {max_e:.3e}, certified near-ties {near}")
+    assert n == G
