@@ -36,6 +36,53 @@ def _check_gates(job):
     return len(gates), err["max_e"], near
 
 
+def _check_learned(job):
+    folder, gates, geom = job
+    import oracle.ispl_lzoom as lzo
+    from oracle import integrate_spectra
+    from tests.parity_util import NEAR_TIE_TOL
+
+    samples = np.load(os.path.join(folder, "samples.npy"), mmap_mode="r")
+    tx = np.load(os.path.join(folder, "tx.npy"), mmap_mode="r")
+    bins = np.load(os.path.join(folder, "bins.npy"), mmap_mode="r")[gates]
+    starts = np.load(os.path.join(folder, "starts.npy"), mmap_mode="r")[gates].astype(np.int64)
+    zoom = np.load(os.path.join(folder, "zoom.npy"), mmap_mode="r")[gates].astype(bool)
+    K = int(np.load(os.path.join(folder, "window.npy")))
+    full = integrate_spectra(samples, tx, gates=gates, **geom)
+    N = full.shape[1]
+    win = np.stack([full[i, (starts[i] + np.arange(K)) % N] for i in range(len(gates))])
+    want = lzo.learned_peaks(win, starts, zoom, full)
+    near = 0
+    for i in np.nonzero(np.asarray(bins) != want)[0]:
+        row = full[i]
+        gap = row[want[i]] - row[bins[i]]
+        assert 0 <= gap <= NEAR_TIE_TOL * max(row[want[i]], row.mean()), (
+            f"gate {gates[i]}: learned bin {bins[i]} vs oracle bin {want[i]} "
+            f"(zoomed {bool(zoom[i])})")
+        near += 1
+    return len(gates), int(zoom.sum()), near
+
+
+def every_gate_learned(samples, tx, bins, starts, zoom, window_bins, *, n_gates, gate_step,
+                       first_gate, fft_len, tx_per_pulse, workers=None):
+    """Checks every gate's learned-zoom peak against the oracle: the argmax of
+    the FP64 spectrum over the gate's window where the gate was zoomed, over
+    the whole spectrum where it fell back.  Returns (gates checked, zoomed
+    gates, certified near-ties)."""
+    if workers is None:
+        workers = max(1, min(len(os.sched_getaffinity(0)), 16))
+    geom = dict(n_gates=n_gates, gate_step=gate_step, first_gate=first_gate, fft_len=fft_len,
+                tx_per_pulse=tx_per_pulse)
+    with tempfile.TemporaryDirectory(prefix="oracle_pool_") as folder:
+        for name, arr in (("samples", samples), ("tx", tx), ("bins", bins), ("starts", starts),
+                          ("zoom", zoom), ("window", np.int64(window_bins))):
+            np.save(os.path.join(folder, name + ".npy"), np.ascontiguousarray(arr))
+        groups = [np.arange(i, n_gates, workers) for i in range(min(workers, n_gates))]
+        with ProcessPoolExecutor(len(groups), mp_context=get_context("spawn")) as pool:
+            res = list(pool.map(_check_learned, [(folder, g, geom) for g in groups]))
+    return sum(r[0] for r in res), sum(r[1] for r in res), sum(r[2] for r in res)
+
+
 def every_gate(samples, tx, spectra, bins, *, n_gates, gate_step, first_gate, fft_len,
                tx_per_pulse, workers=None):
     """Checks every gate's spectrum and peak against the oracle; returns

@@ -86,3 +86,46 @@ def test_full_fft_peaks_agree_with_the_oracle_on_one_dataset():
         gap = ref[g, rb[g]] - ref[g, got[g]]
         assert gap <= 2e-5 * max(ref[g, rb[g]], ref[g].mean()), g
     ctx.close()
+
+
+def test_trained_learned_zoom_at_full_size_every_gate():
+    """The trained learned zoom at the benchmarked size (1000 pulses x 1000
+    gates, every 50th range cell without a line, so that the fallback runs
+    too): every gate's peak against the FP64 oracle, run in worker processes
+    on the host cores."""
+    ensure_library()
+    import paper_2311_18737_amd as ispl
+    from paper_2311_18737_amd.zoom_training import EVAL_SEED0, load_weights
+    from synth import CONFIGS
+    from tests.oracle_pool import every_gate_learned
+
+    cfg = CONFIGS["zoom"].replace(n_pulses=1000, n_gates=1000, silent_every=50)
+    print("case learned zoom 1000 x 1000: drawing", flush=True)
+    d = make_dataset(cfg, EVAL_SEED0 + 500)
+    net = ispl.Net(1)
+    net.set_params(load_weights())
+    geo = dict(code_len=cfg.code_len, n_gates=cfg.n_gates, gate_step=cfg.gate_step,
+               first_gate=cfg.first_gate, pulse_stride=cfg.pulse_stride,
+               sample_type=cfg.sample_type, max_pulses=cfg.n_pulses)
+    K = 256
+    lz = ispl.LearnedZoom(net, fft_len=cfg.fft_len, window_bins=K, threshold=0.9, **geo)
+    xs = torch.from_numpy(d.samples).to("cuda:0")
+    xt = torch.from_numpy(d.tx).to("cuda:0")
+    bins, _ = lz.peaks(xs, xt)
+    torch.cuda.synchronize()
+    v = lz.view()
+    G = cfg.n_gates
+    zl, counts = v["zoom_list"].cpu().numpy(), v["counts"].cpu().numpy()
+    zoom = np.zeros(G, dtype=bool)
+    zoom[zl[:counts[0]]] = True
+    starts = v["bin_start"].cpu().numpy()
+    print(f"  zoomed {counts[0]}, fallback {counts[1]}; oracle on every gate", flush=True)
+    assert counts[1] > 0 and counts[0] + counts[1] == G
+    n, n_zoom, near = every_gate_learned(d.samples, d.tx, bins.cpu().numpy(), starts, zoom, K,
+                                         n_gates=G, gate_step=cfg.gate_step,
+                                         first_gate=cfg.first_gate, fft_len=cfg.fft_len,
+                                         tx_per_pulse=True)
+    print(f"  every gate: {n} gates ({n_zoom} zoomed), certified near-ties {near}", flush=True)
+    assert n == G and n_zoom == counts[0]
+    lz.close()
+    net.close()

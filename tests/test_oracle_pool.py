@@ -37,3 +37,25 @@ def test_pool_catches_a_wrong_bin_and_a_wrong_peak():
     wrong[7] = (wrong[7] + 300) % geom["fft_len"]
     with pytest.raises(AssertionError):
         every_gate(samples, tx, s32, wrong, workers=2, **geom)
+
+
+def test_learned_runner_accepts_oracle_peaks_and_catches_a_moved_one():
+    import oracle.ispl_lzoom as lzo
+    from tests.oracle_pool import every_gate_learned
+
+    N, L, G, P, s, K = 2048, 100, 11, 4, 13, 256
+    stride = (G - 1) * s + L
+    samples, tx = random_inputs(P, stride, L, sample_type="c64", seed=5)
+    geom = dict(n_gates=G, gate_step=s, first_gate=0, fft_len=N, tx_per_pulse=True)
+    full = integrate_spectra(samples, tx, **geom)
+    rng = np.random.default_rng(1)
+    starts = rng.integers(0, N, G)
+    zoom = rng.random(G) < 0.6
+    win = np.stack([full[g, (starts[g] + np.arange(K)) % N] for g in range(G)])
+    want = lzo.learned_peaks(win, starts, zoom, full).astype(np.int32)
+    n, n_zoom, near = every_gate_learned(samples, tx, want, starts, zoom, K, workers=3, **geom)
+    assert (n, n_zoom, near) == (G, int(zoom.sum()), 0)
+    bad = want.copy()
+    bad[5] = (bad[5] + 7) % N
+    with pytest.raises(AssertionError):
+        every_gate_learned(samples, tx, bad, starts, zoom, K, workers=2, **geom)
