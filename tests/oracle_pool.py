@@ -83,6 +83,43 @@ def every_gate_learned(samples, tx, bins, starts, zoom, window_bins, *, n_gates,
     return sum(r[0] for r in res), sum(r[1] for r in res), sum(r[2] for r in res)
 
 
+def _check_windows(job):
+    folder, gates, geom = job
+    from oracle import integrate_spectra
+    from tests.parity_util import spectra_error
+
+    samples = np.load(os.path.join(folder, "samples.npy"), mmap_mode="r")
+    tx = np.load(os.path.join(folder, "tx.npy"), mmap_mode="r")
+    got = np.asarray(np.load(os.path.join(folder, "windows.npy"), mmap_mode="r")[gates])
+    starts = np.load(os.path.join(folder, "starts.npy"), mmap_mode="r")[gates].astype(np.int64)
+    tol = float(np.load(os.path.join(folder, "tol.npy")))
+    full = integrate_spectra(samples, tx, gates=gates, **geom)
+    N, K = full.shape[1], got.shape[1]
+    ref = np.stack([full[i, (starts[i] + np.arange(K)) % N] for i in range(len(gates))])
+    err = spectra_error(got, ref)
+    assert err["max_e"] <= tol, f"gates {gates[0]}::{len(gates)}: window error {err}"
+    return len(gates), err["max_e"]
+
+
+def every_gate_windows(samples, tx, windows, starts, tol, *, n_gates, gate_step, first_gate,
+                       fft_len, tx_per_pulse, workers=None):
+    """Checks every gate's window spectrum (bins start, start + 1, ... mod N)
+    element by element against the oracle's, to `tol` under parity_util's
+    per-bin rule.  Returns (gates checked, largest per-bin error)."""
+    if workers is None:
+        workers = max(1, min(len(os.sched_getaffinity(0)), 16))
+    geom = dict(n_gates=n_gates, gate_step=gate_step, first_gate=first_gate, fft_len=fft_len,
+                tx_per_pulse=tx_per_pulse)
+    with tempfile.TemporaryDirectory(prefix="oracle_pool_") as folder:
+        for name, arr in (("samples", samples), ("tx", tx), ("windows", windows),
+                          ("starts", starts), ("tol", np.float64(tol))):
+            np.save(os.path.join(folder, name + ".npy"), np.ascontiguousarray(arr))
+        groups = [np.arange(i, n_gates, workers) for i in range(min(workers, n_gates))]
+        with ProcessPoolExecutor(len(groups), mp_context=get_context("spawn")) as pool:
+            res = list(pool.map(_check_windows, [(folder, g, geom) for g in groups]))
+    return sum(r[0] for r in res), max(r[1] for r in res)
+
+
 def every_gate(samples, tx, spectra, bins, *, n_gates, gate_step, first_gate, fft_len,
                tx_per_pulse, workers=None):
     """Checks every gate's spectrum and peak against the oracle; returns

@@ -59,3 +59,22 @@ def test_learned_runner_accepts_oracle_peaks_and_catches_a_moved_one():
     bad[5] = (bad[5] + 7) % N
     with pytest.raises(AssertionError):
         every_gate_learned(samples, tx, bad, starts, zoom, K, workers=2, **geom)
+
+
+def test_window_runner_accepts_oracle_windows_and_catches_an_error():
+    from tests.oracle_pool import every_gate_windows
+
+    N, L, G, P, s, K = 2048, 100, 7, 3, 11, 128
+    stride = (G - 1) * s + L
+    samples, tx = random_inputs(P, stride, L, sample_type="ci16", seed=6, amplitude=1000.0)
+    geom = dict(n_gates=G, gate_step=s, first_gate=0, fft_len=N, tx_per_pulse=True)
+    full = integrate_spectra(samples, tx, **geom)
+    starts = np.random.default_rng(2).integers(0, N, G)
+    win = np.stack([full[g, (starts[g] + np.arange(K)) % N] for g in range(G)]).astype(np.float32)
+    n, max_e = every_gate_windows(samples, tx, win, starts, 1e-5, workers=2, **geom)
+    assert n == G and max_e < 1e-7
+    bad = win.copy()
+    k = int(np.argmax(bad[3]))
+    bad[3, k] *= 1.0001
+    with pytest.raises(AssertionError):
+        every_gate_windows(samples, tx, bad, starts, 1e-5, workers=2, **geom)

@@ -234,3 +234,30 @@ def test_zoom_rejects_bad_windows(ispl):
             ispl.Zoom(ctx, K, prec)
         assert ei.value.status == ispl.ISPL_ERR_INVALID_ARG
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp16x3", "bf16x3"])
+def test_full_size_every_gate(ispl, precision):
+    """The zoom at the benchmarked size (1000 pulses x 1000 gates, L = 256,
+    N = 16384, 256-bin windows at seeded random starts), one launch with the
+    production plan: every gate's window element by element against the FP64
+    oracle (worker processes on the host cores)."""
+    from synth import CONFIGS
+    from tests.oracle_pool import every_gate_windows
+
+    cfg = CONFIGS["zoom"].replace(n_pulses=1000, n_gates=1000)
+    say(f"case zoom 1000 x 1000 {precision}: drawing")
+    d = make_dataset(cfg, 3)
+    N, K, G = cfg.fft_len, 256, cfg.n_gates
+    starts = np.random.default_rng(4).integers(0, N, size=G)
+    ctx, z, out, *_ = run_zoom(ispl, d.samples, d.tx, starts, L=cfg.code_len, N=N, G=G,
+                               s=cfg.gate_step, g0=cfg.first_gate, stride=cfg.pulse_stride,
+                               st=cfg.sample_type, K=K, precision=precision)
+    say("  oracle on every gate")
+    n, max_e = every_gate_windows(d.samples, d.tx, out.cpu().numpy(), starts, TOL[precision],
+                                  n_gates=G, gate_step=cfg.gate_step, first_gate=cfg.first_gate,
+                                  fft_len=N, tx_per_pulse=True)
+    say(f"  every gate: {n} gates, max e {max_e:.3e}")
+    assert n == G
+    z.close()
+    ctx.close()
