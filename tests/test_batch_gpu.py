@@ -268,3 +268,39 @@ def test_random_modes_equal_each_mode_and_the_oracle(ispl, seed, n_modes, st):
         err = spectra_error(r.cpu().numpy(), want)
         assert err["max_e"] <= 1e-5, (g, err)
     b.close()
+
+
+def test_full_size_batch_every_gate(ispl):
+    """The uneven batch at its benchmarked size (four experiments of 500
+    pulses: L 128/480/1000/2000, N 4096...32768, 200/600/1000/2000 gates,
+    complex64) from one graph launch of the automatic plan: every gate of every
+    experiment, spectrum and peak, against the FP64 oracle (worker processes
+    on the host cores)."""
+    from synth import CONFIGS, make_dataset
+    from tests.oracle_pool import every_gate
+
+    cfgs = [CONFIGS[n] for n in ("batch_a", "batch_b", "batch_c", "batch_d")]
+    ds = []
+    for c in cfgs:
+        say(f"case full-size batch: drawing {c.name}")
+        ds.append(make_dataset(c, 0))
+    geo = [dict(code_len=c.code_len, fft_len=c.fft_len, n_gates=c.n_gates, gate_step=c.gate_step,
+                first_gate=c.first_gate, pulse_stride=c.pulse_stride, max_pulses=c.n_pulses)
+           for c in cfgs]
+    inputs = [(torch.from_numpy(d.samples).to(DEV), torch.from_numpy(d.tx).to(DEV)) for d in ds]
+    outs = [torch.empty((c.n_gates, c.fft_len), dtype=torch.float32, device=DEV) for c in cfgs]
+    b = ispl.Batch(geo)
+    b.integrate(inputs, outs, use_graph=True)
+    torch.cuda.synchronize()
+    b.close()
+    for c, g, d, o in zip(cfgs, geo, ds, outs):
+        ctx = ispl.Context(**g)
+        bins, _ = ctx.find_plasma_line(o)
+        torch.cuda.synchronize()
+        ctx.close()
+        say(f"  oracle on every gate of {c.name}")
+        n, max_e, near = every_gate(d.samples, d.tx, o.cpu().numpy(), bins.cpu().numpy(),
+                                    n_gates=c.n_gates, gate_step=c.gate_step,
+                                    first_gate=c.first_gate, fft_len=c.fft_len, tx_per_pulse=True)
+        say(f"  {c.name}: {n} gates, max e {max_e:.3e}, certified near-ties {near}")
+        assert n == c.n_gates
