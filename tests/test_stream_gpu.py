@@ -22,6 +22,11 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
 @pytest.fixture(scope="module")
 def ispl():
     ensure_library()
@@ -138,3 +143,47 @@ def test_stream_slot_rules(ispl):
     torch.cuda.synchronize()
     assert torch.count_nonzero(out).item() == 0
     ing.close()
+
+
+def test_full_size_stream_every_gate(ispl):
+    """The headline workload (1000 pulses x 1000 gates, int16) streamed from
+    pinned host slots in the batches the benchmark uses (16, 64, 256, 664
+    pulses): every gate's spectrum and peak against the FP64 oracle (worker
+    processes on the host cores)."""
+    from synth import CONFIGS, make_dataset
+    from tests.oracle_pool import every_gate
+
+    cfg = CONFIGS["realistic"]
+    say("case streamed realistic workload: drawing 1000 pulses")
+    d = make_dataset(cfg, 1)
+    batches = [16, 64, 256, 664]
+    assert sum(batches) == cfg.n_pulses
+    ing = ispl.StreamIngest(code_len=cfg.code_len, fft_len=cfg.fft_len, n_gates=cfg.n_gates,
+                            gate_step=cfg.gate_step, first_gate=cfg.first_gate,
+                            pulse_stride=cfg.pulse_stride, sample_type=cfg.sample_type,
+                            slot_pulses=max(batches), n_slots=len(batches))
+    out = torch.empty((cfg.n_gates, cfg.fft_len), dtype=torch.float32, device=DEV)
+    p0 = 0
+    for k, n in enumerate(batches):
+        hs, hc = ing.slot(k)
+        hs[:n] = d.samples[p0:p0 + n]
+        hc[:n] = d.tx[p0:p0 + n]
+        p0 += n
+    for k, n in enumerate(batches):
+        ing.submit(k, n, out, accumulate=k > 0)
+    ing.sync()
+    torch.cuda.synchronize()
+    ing.close()
+    ctx = ispl.Context(code_len=cfg.code_len, fft_len=cfg.fft_len, n_gates=cfg.n_gates,
+                       gate_step=cfg.gate_step, first_gate=cfg.first_gate,
+                       pulse_stride=cfg.pulse_stride, sample_type=cfg.sample_type,
+                       max_pulses=cfg.n_pulses)
+    bins, _ = ctx.find_plasma_line(out)
+    torch.cuda.synchronize()
+    ctx.close()
+    say("  oracle on every gate")
+    n, max_e, near = every_gate(d.samples, d.tx, out.cpu().numpy(), bins.cpu().numpy(),
+                                n_gates=cfg.n_gates, gate_step=cfg.gate_step,
+                                first_gate=cfg.first_gate, fft_len=cfg.fft_len, tx_per_pulse=True)
+    say(f"  every gate: {n} gates, max e {max_e:.3e}, certified near-ties {near}")
+    assert n == cfg.n_gates
